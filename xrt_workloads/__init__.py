@@ -1,0 +1,171 @@
+"""Seeded synthetic inputs: line geometries and ellipse phantoms.
+
+This module only draws inputs.  It holds none of the operator's arithmetic
+(no footprint, no projection), so that the FP64 oracle and the HIP library can
+both be fed from it without sharing any part of the method.
+
+Geometry conventions (the line of eq. (1): {t theta + y theta^perp},
+theta = (cos t, sin t), theta^perp = (sin t, -cos t)):
+
+* parallel beam: angles t_m = m*pi/n_angles (m < n_angles, endpoint of [0, pi)
+  excluded), computed in FP64 and rounded once to float32; detector bins
+  y_j = (j - (n_bins-1)/2) * delta, centred on the origin; angle-major order.
+* fan beam: source s on a circle of radius R at beta_m = 2*pi*m/n_src; bins on
+  an equiangular arc centred on the ray through the origin, fan angles
+  gamma_j = (j - (n_bins-1)/2) * 2*gamma_max/n_bins with
+  gamma_max = asin(R_fov/R), R_fov = sqrt(2)*N/2 + (degree+1)/2 (the fan
+  covers the padded grid).  Lines are delivered as float32 endpoint pairs
+  (source, source + 2R*direction), source-major.
+* random lines: t ~ U[0, pi), y ~ U[-N/2, N/2].
+
+Phantom: E ellipses with centres U[-24,24]^2, semi-axes U[3,20] each,
+rotation U[0,pi), amplitude U[-0.5,1], every length scaled by N/64; the
+coefficient at grid centre x_k is the sum of the amplitudes of the ellipses
+that contain x_k (no prefilter); optional i.i.d. texture N(0, sigma^2) with
+sigma = 0.1 (the N(0, 0.01) of the workload read as a variance).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+def parallel_beam(n_angles: int, n_bins: int, delta: float = 1.0, angle_range: float = math.pi):
+    m = np.arange(n_angles, dtype=np.float64)
+    th = (m * (angle_range / n_angles)).astype(np.float32)
+    j = np.arange(n_bins, dtype=np.float64)
+    yb = ((j - 0.5 * (n_bins - 1)) * delta).astype(np.float32)
+    theta = np.repeat(th, n_bins)
+    y = np.tile(yb, n_angles)
+    return {"kind": "theta_y", "theta": theta, "y": y}
+
+
+def fan_half_angle(N: int, degree: int, radius: float) -> float:
+    r_fov = math.sqrt(2.0) * N / 2.0 + (degree + 1) / 2.0
+    return math.asin(min(1.0, r_fov / radius))
+
+
+def fan_beam(n_src: int, n_bins: int, radius: float, N: int, degree: int):
+    gmax = fan_half_angle(N, degree, radius)
+    beta = 2.0 * math.pi * np.arange(n_src, dtype=np.float64) / n_src
+    gam = (np.arange(n_bins, dtype=np.float64) - 0.5 * (n_bins - 1)) * (2.0 * gmax / n_bins)
+    sx = radius * np.cos(beta)
+    sy = radius * np.sin(beta)
+    # central direction points from the source to the origin
+    phi = beta[:, None] + math.pi + gam[None, :]
+    dx = np.cos(phi)
+    dy = np.sin(phi)
+    ep = np.empty((n_src, n_bins, 4), dtype=np.float64)
+    ep[..., 0] = sx[:, None]
+    ep[..., 1] = sy[:, None]
+    ep[..., 2] = sx[:, None] + 2.0 * radius * dx
+    ep[..., 3] = sy[:, None] + 2.0 * radius * dy
+    return {"kind": "endpoints", "endpoints": ep.reshape(-1, 4).astype(np.float32)}
+
+
+def random_lines(m: int, N: int, seed: int):
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0.0, math.pi, size=m).astype(np.float32)
+    y = rng.uniform(-N / 2.0, N / 2.0, size=m).astype(np.float32)
+    return {"kind": "theta_y", "theta": theta, "y": y}
+
+
+def ellipse_phantom(N: int, n_ellipses: int, seed: int, texture_sigma: float = 0.0,
+                    nx: int | None = None, ny: int | None = None):
+    nx = N if nx is None else nx
+    ny = N if ny is None else ny
+    rng = np.random.default_rng(seed)
+    sc = N / 64.0
+    cen = rng.uniform(-24.0, 24.0, size=(n_ellipses, 2)) * sc
+    ax = rng.uniform(3.0, 20.0, size=(n_ellipses, 2)) * sc
+    rot = rng.uniform(0.0, math.pi, size=n_ellipses)
+    amp = rng.uniform(-0.5, 1.0, size=n_ellipses)
+    x1 = np.arange(nx, dtype=np.float64) - 0.5 * (nx - 1)
+    x2 = np.arange(ny, dtype=np.float64) - 0.5 * (ny - 1)
+    X1, X2 = np.meshgrid(x1, x2)  # [ny, nx]
+    img = np.zeros((ny, nx), dtype=np.float64)
+    for e in range(n_ellipses):
+        c, s = math.cos(rot[e]), math.sin(rot[e])
+        d1 = X1 - cen[e, 0]
+        d2 = X2 - cen[e, 1]
+        p = (c * d1 + s * d2) / ax[e, 0]
+        q = (-s * d1 + c * d2) / ax[e, 1]
+        img[p * p + q * q <= 1.0] += amp[e]
+    if texture_sigma > 0.0:
+        img += rng.normal(0.0, texture_sigma, size=img.shape)
+    return img.astype(np.float32)
+
+
+def concat_lines(*specs):
+    """Concatenate line sets into one endpoint list (theta/y lines are turned
+    into endpoint pairs at distance +-L along the line)."""
+    eps = []
+    for sp in specs:
+        if sp["kind"] == "endpoints":
+            eps.append(np.asarray(sp["endpoints"], dtype=np.float32))
+        else:
+            raise ValueError("concat_lines takes endpoint sets only")
+    return {"kind": "endpoints", "endpoints": np.concatenate(eps, axis=0)}
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    N: int
+    degree: int
+    seed: int
+    description: str
+
+
+# Workloads (seeds fixed; recorded with every result)
+SMALL_PARALLEL = Workload("parallel-64-deg1", 64, 1, 1,
+                          "64x64 degree-1, parallel beam 90 angles x 96 bins, 10-ellipse phantom")
+MEDIUM = Workload("mixed-512", 512, 3, 2,
+                  "512x512 degrees 0-3, parallel 360x768 + fan 360x768 (R=1000), "
+                  "30 ellipses + texture")
+LARGE = Workload("fan+random-2048-cubic", 2048, 3, 5,
+                 "2048x2048 cubic, fan 1440x3072 (R=4000) + 4,423,680 random lines")
+
+
+def small_parallel():
+    """64x64 degree-1 grid; 90 angles in [0, pi) x 96 bins of spacing 1."""
+    w = SMALL_PARALLEL
+    coeffs = ellipse_phantom(64, 10, seed=w.seed)
+    return coeffs, parallel_beam(90, 96, 1.0)
+
+
+def medium_parallel():
+    w = MEDIUM
+    coeffs = ellipse_phantom(512, 30, seed=w.seed, texture_sigma=0.1)
+    return coeffs, parallel_beam(360, 768, 1.0)
+
+
+def medium_fan(degree: int):
+    w = MEDIUM
+    coeffs = ellipse_phantom(512, 30, seed=w.seed, texture_sigma=0.1)
+    return coeffs, fan_beam(360, 768, 1000.0, 512, degree)
+
+
+def large_lines(n_src: int = 1440, n_bins: int = 3072, n_random: int | None = None,
+                N: int = 2048, degree: int = 3, seed: int = 5):
+    """Fan (R = 4000, same R/N as the 512 case) followed by random lines, as one
+    endpoint list."""
+    fan = fan_beam(n_src, n_bins, 4000.0, N, degree)
+    nr = n_src * n_bins if n_random is None else n_random
+    rnd = random_lines(nr, N, seed)
+    th = rnd["theta"].astype(np.float64)
+    y = rnd["y"].astype(np.float64)
+    # a point on the line and a second point one radius along it
+    px = y * np.sin(th)
+    py = -y * np.cos(th)
+    L = float(N)
+    ep = np.stack([px - L * np.cos(th), py - L * np.sin(th),
+                   px + L * np.cos(th), py + L * np.sin(th)], axis=1).astype(np.float32)
+    return {"kind": "endpoints",
+            "endpoints": np.concatenate([fan["endpoints"], ep], axis=0)}, fan["endpoints"].shape[0]
+
+
+def large_phantom(N: int = 2048, seed: int = 5):
+    return ellipse_phantom(N, 30, seed=seed, texture_sigma=0.1)
