@@ -1,0 +1,139 @@
+/*
+ * xrt.h -- x-ray transform of tensor-product B-spline images (degree 0..3)
+ * over an arbitrary list of lines, and its exact adjoint, on AMD Instinct
+ * MI355X (gfx950).  C ABI of libxrt.so.
+ *
+ * Mathematical definition (Haouchat et al., "Generalized Ray Tracing with Basis
+ * Functions for Tomographic Projections"):
+ *
+ *   image       f = sum_k c_k phi((x - x_k)/h),  phi = beta^n (x) beta^n
+ *               (eq. (3) with the tensor B-spline generator of Section III-C);
+ *   line        {t theta + y theta_perp}, theta = (cos t, sin t),
+ *               theta_perp = (sin t, -cos t)                      (eq. (1));
+ *   forward     s_m = P_{theta_m}{f}(y_m)
+ *                   = sum_k c_k h phi_{theta_m}((y_m - <x_k, theta_m_perp>)/h)
+ *               (eqs. (2) and (4); the matrix H_phi of Section IV-A);
+ *   footprint   phi_theta = beta^n_{|cos t|} * beta^n_{|sin t|},
+ *               beta_a(x) = beta(x/a)/a  (Proposition 1 / eq. (6));
+ *   adjoint     (H^T s)_k = sum_m s_m h phi_{theta_m}((y_m - <x_k, theta_m_perp>)/h)
+ *               (the matched back-projection of Section II-B).
+ *
+ * Grid: coefficients are a row-major float32 array [ny][nx]; element (j, i)
+ * sits at x_ij = (cx + (i - (nx-1)/2) h, cy + (j - (ny-1)/2) h): column i along
+ * x1, row j along x2.  The image extends (n+1)h/2 beyond the outer centres;
+ * lines that only graze that margin are included.
+ *
+ * Conventions for every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller; the library
+ *     never frees them.  Outputs are overwritten, not accumulated.  Inputs and
+ *     outputs must not alias.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Entry points that create a plan (xrt_plan_create, and xrt_forward /
+ *     xrt_adjoint, which build a temporary plan) synchronise with `stream` once
+ *     to read the plan header back; xrt_plan_forward / xrt_plan_adjoint do not
+ *     synchronise.
+ *   - Argument errors are returned synchronously before any work is enqueued.
+ *     A failing HIP call returns XRT_EHIP; xrt_last_error() then gives the HIP
+ *     message for the calling thread.
+ *   - Arithmetic is float32 with float64 line geometry; results match the
+ *     plain FP64 definition above to about 1e-6 relative (L2 over a sinogram).
+ */
+#ifndef XRT_H
+#define XRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XRT_OK = 0,
+    XRT_EINVAL = -1,  /* null pointer, negative count, bad grid, non-finite or degenerate line */
+    XRT_EDEGREE = -2, /* degree outside 0..3 */
+    XRT_ESIZE = -3,   /* grid or line count beyond the supported range */
+    XRT_ENOMEM = -4,  /* device allocation failed; nothing is left allocated */
+    XRT_EHIP = -5,    /* a HIP call or kernel launch failed */
+    XRT_EPLAN = -6    /* plan and call disagree (null or foreign plan) */
+} xrt_status;
+
+/* Coefficient grid.  nx, ny >= 1 and <= 32768; spacing h > 0 (the paper
+ * takes h = 1); (cx, cy) is the centre of the grid of centres. */
+typedef struct {
+    int32_t nx, ny;
+    double spacing;
+    double cx, cy;
+} xrt_grid;
+
+typedef enum {
+    XRT_LINES_THETA_Y = 0,  /* theta[n], y[n]: the (theta, y) of eq. (1), float32 */
+    XRT_LINES_ENDPOINTS = 1 /* endpoints[n][4] = (px, py, qx, qy), float32: the infinite
+                               line through p and q; p == q is an error */
+} xrt_line_kind;
+
+/* A list of n lines (0 <= n < 2^31).  Pointers are device pointers; only the
+ * ones of the chosen kind are read. */
+typedef struct {
+    int32_t kind;
+    int64_t n;
+    const float* theta;
+    const float* y;
+    const float* endpoints;
+} xrt_lines;
+
+/* Opaque plan: the line list canonicalised in FP64 and sorted into
+ * (orientation, slope bin, crossing bucket) order, the bucket offsets the
+ * adjoint uses to find the lines crossing each image tile, and a workspace for
+ * the per-call coefficient layouts.  The geometry part is immutable; the
+ * workspace is reused by every call, so calls with one plan must not overlap
+ * (use one plan per concurrent stream). */
+typedef struct xrt_plan xrt_plan;
+
+/* Forward projection (eq. (4)) of coeffs [g.ny][g.nx] along every line into
+ * sino [lines->n].  Builds and frees a temporary plan (synchronises once). */
+xrt_status xrt_forward(const float* coeffs, xrt_grid g, int degree, const xrt_lines* lines,
+                       float* sino, void* stream);
+
+/* Adjoint (back-projection) of sino [lines->n] into coeffs_out [g.ny][g.nx].
+ * Builds and frees a temporary plan (synchronises once). */
+xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xrt_grid g,
+                       float* coeffs_out, void* stream);
+
+/* Builds a plan for (grid, degree, lines).  The line arrays are read during
+ * the call only.  On error *out is NULL and nothing stays allocated. */
+xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream,
+                           xrt_plan** out);
+
+/* Forward / adjoint with a plan: the hot path.  No synchronisation, no
+ * allocation. */
+xrt_status xrt_plan_forward(const xrt_plan* p, const float* coeffs, float* sino, void* stream);
+xrt_status xrt_plan_adjoint(const xrt_plan* p, const float* sino, float* coeffs_out,
+                            void* stream);
+
+/* Number of lines of the plan, and of those that cross the padded grid. */
+xrt_status xrt_plan_info(const xrt_plan* p, int64_t* n_lines, int64_t* n_crossing);
+
+/* Exact number of (line, centre) pairs inside the footprint support
+ * (|u| < (n+1)(|cos|+|sin|)/2): the structural nonzeros of H_phi, i.e. the
+ * basis evaluations one forward or adjoint pass performs.  Counted on the
+ * device; synchronises with `stream`. */
+xrt_status xrt_plan_nnz(const xrt_plan* p, int64_t* nnz, void* stream);
+
+/* Frees the plan (waits for the device to finish using it).  NULL is a no-op. */
+void xrt_plan_destroy(xrt_plan* p);
+
+/* Static description of a status code. */
+const char* xrt_status_string(xrt_status st);
+
+/* Message of the last XRT_EHIP / XRT_ENOMEM failure on the calling thread
+ * ("" if none). */
+const char* xrt_last_error(void);
+
+/* Library version "major.minor.patch". */
+const char* xrt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XRT_H */

@@ -1,0 +1,148 @@
+"""ctypes binding of libxrt.so: argument marshalling only.
+
+Every entry point has the name of its C counterpart in include/xrt.h.  Array
+arguments are raw device addresses (ints) and the stream is a hipStream_t
+handle (int, 0 for the null stream).  The library is loaded from this package
+directory; if it is missing the import fails loudly, since there is no other
+implementation of the operator on the product path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxrt.so")
+
+XRT_OK = 0
+XRT_EINVAL = -1
+XRT_EDEGREE = -2
+XRT_ESIZE = -3
+XRT_ENOMEM = -4
+XRT_EHIP = -5
+XRT_EPLAN = -6
+
+XRT_LINES_THETA_Y = 0
+XRT_LINES_ENDPOINTS = 1
+
+# every symbol declared in include/xrt.h
+EXPORTS = ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
+           "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_plan_destroy",
+           "xrt_status_string", "xrt_last_error", "xrt_version")
+
+
+class XrtGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("spacing", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double)]
+
+
+class XrtLines(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("theta", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("endpoints", ctypes.c_void_p)]
+
+
+class XrtError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {status_string(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2503_20907_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    lib.xrt_forward.argtypes = [vp, XrtGrid, i32, ctypes.POINTER(XrtLines), vp, vp]
+    lib.xrt_adjoint.argtypes = [vp, ctypes.POINTER(XrtLines), i32, XrtGrid, vp, vp]
+    lib.xrt_plan_create.argtypes = [XrtGrid, i32, ctypes.POINTER(XrtLines), vp,
+                                    ctypes.POINTER(vp)]
+    lib.xrt_plan_forward.argtypes = [vp, vp, vp, vp]
+    lib.xrt_plan_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.xrt_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.xrt_plan_nnz.argtypes = [vp, ctypes.POINTER(i64), vp]
+    lib.xrt_plan_destroy.argtypes = [vp]
+    lib.xrt_plan_destroy.restype = None
+    lib.xrt_status_string.argtypes = [i32]
+    lib.xrt_status_string.restype = ctypes.c_char_p
+    lib.xrt_last_error.argtypes = []
+    lib.xrt_last_error.restype = ctypes.c_char_p
+    lib.xrt_version.restype = ctypes.c_char_p
+    for name in ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
+                 "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def status_string(st: int) -> str:
+    return load().xrt_status_string(int(st)).decode()
+
+
+def last_error() -> str:
+    return load().xrt_last_error().decode()
+
+
+def check(st: int, where: str):
+    if st != XRT_OK:
+        raise XrtError(st, where, last_error() if st in (XRT_EHIP, XRT_ENOMEM) else "")
+
+
+def xrt_forward(coeffs, grid: XrtGrid, degree: int, lines: XrtLines, sino, stream) -> int:
+    return load().xrt_forward(coeffs, grid, int(degree), ctypes.byref(lines), sino, stream)
+
+
+def xrt_adjoint(sino, lines: XrtLines, degree: int, grid: XrtGrid, coeffs_out, stream) -> int:
+    return load().xrt_adjoint(sino, ctypes.byref(lines), int(degree), grid, coeffs_out, stream)
+
+
+def xrt_plan_create(grid: XrtGrid, degree: int, lines: XrtLines, stream):
+    out = ctypes.c_void_p()
+    st = load().xrt_plan_create(grid, int(degree), ctypes.byref(lines), stream,
+                                ctypes.byref(out))
+    return st, out.value
+
+
+def xrt_plan_forward(plan, coeffs, sino, stream) -> int:
+    return load().xrt_plan_forward(plan, coeffs, sino, stream)
+
+
+def xrt_plan_adjoint(plan, sino, coeffs_out, stream) -> int:
+    return load().xrt_plan_adjoint(plan, sino, coeffs_out, stream)
+
+
+def xrt_plan_info(plan):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    st = load().xrt_plan_info(plan, ctypes.byref(a), ctypes.byref(b))
+    return st, a.value, b.value
+
+
+def xrt_plan_nnz(plan, stream):
+    a = ctypes.c_int64()
+    st = load().xrt_plan_nnz(plan, ctypes.byref(a), stream)
+    return st, a.value
+
+
+def xrt_plan_destroy(plan) -> None:
+    load().xrt_plan_destroy(plan)
+
+
+def xrt_status_string(st: int) -> str:
+    return status_string(st)
+
+
+def xrt_last_error() -> str:
+    return last_error()
+
+
+def xrt_version() -> str:
+    return load().xrt_version().decode()

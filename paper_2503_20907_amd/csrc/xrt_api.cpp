@@ -1,0 +1,436 @@
+// Host side of libxrt.so: argument checks, plan construction, dispatch, and
+// the FP64 construction of the knot-transition table used by the kernels.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "xrt_internal.h"
+
+using namespace xrt;
+
+namespace {
+
+constexpr uint64_t kPlanMagic = 0x58525450'4c414e31ull;  // "XRTPLAN1"
+constexpr int kMaxGrid = 32768;
+
+thread_local char g_last_error[256] = "";
+
+void set_error(const char* what, hipError_t e)
+{
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+}
+
+// ----------------------------------------------------------- E table (FP64)
+// G(z) = sum_l delta_l (z - kappa_l)_+^(2n+1) / (2n+1)!  is the (n+1)-fold
+// integral of beta^n (kappa_l = l - (n+1)/2, delta_l = (-1)^l C(n+1,l));
+// the kernels use g(zeta) = G(-zeta) for zeta in [0, (n+1)/2].  On that range
+// only the knots left of 0 contribute and the terms are O(1), so the sum is
+// well conditioned in FP64.
+double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// sum_l delta_l (z - kappa_l)_+^p / p!.  For p = 0 the step at a knot is
+// taken as its right limit in z when right_limit is set (the value at the
+// knot from z > knot), and as its left limit otherwise.
+double Gpow(int n, double z, int p, bool right_limit = false)
+{
+    double fac = 1.0;
+    for (int i = 2; i <= p; ++i) fac *= i;
+    double acc = 0.0;
+    for (int l = 0; l <= n + 1; ++l) {
+        double x = z - (l - 0.5 * (n + 1));
+        if (x < 0.0 || (x == 0.0 && !(p == 0 && right_limit))) continue;
+        double term = binom(n + 1, l) * (p == 0 ? 1.0 : pow(x, p)) / fac;
+        acc += (l & 1) ? -term : term;
+    }
+    return acc;
+}
+
+float g_tab[4][kTabMax * 4];
+int g_tab_n[4];
+std::once_flag g_tab_once;
+
+void build_tables()
+{
+    for (int n = 0; n <= 3; ++n) {
+        const int nint = kTabPerUnit * (n + 1) / 2;
+        const double dz = 1.0 / kTabPerUnit;
+        for (int i = 0; i < nint; ++i) {
+            // g(zeta) = G(-zeta), g'(zeta) = -G'(-zeta); cubic Hermite in tau.
+            // The end slopes are limits from inside the interval: at zeta0 the
+            // limit from zeta > zeta0 (z < -zeta0), at zeta1 the limit from
+            // zeta < zeta1 (z > -zeta1); they differ only where G' jumps
+            // (degree 0 at the end of the support).
+            const double z0 = i * dz, z1 = (i + 1) * dz;
+            const double g0 = Gpow(n, -z0, 2 * n + 1), g1 = Gpow(n, -z1, 2 * n + 1);
+            const double d0 = -Gpow(n, -z0, 2 * n, false) * dz;
+            const double d1 = -Gpow(n, -z1, 2 * n, true) * dz;
+            const double a0 = g0, a1 = d0;
+            const double a2 = 3.0 * (g1 - g0) - 2.0 * d0 - d1;
+            const double a3 = 2.0 * (g0 - g1) + d0 + d1;
+            g_tab[n][4 * i + 0] = (float)a0;
+            g_tab[n][4 * i + 1] = (float)a1;
+            g_tab[n][4 * i + 2] = (float)a2;
+            g_tab[n][4 * i + 3] = (float)a3;
+        }
+        for (int c = 0; c < 4; ++c) g_tab[n][4 * nint + c] = 0.f;  // |z| >= (n+1)/2
+        g_tab_n[n] = nint + 1;
+    }
+}
+
+bool finite_grid(const xrt_grid& g)
+{
+    return isfinite(g.spacing) && isfinite(g.cx) && isfinite(g.cy);
+}
+
+xrt_status check_grid(const xrt_grid& g)
+{
+    if (g.nx <= 0 || g.ny <= 0 || !(g.spacing > 0.0) || !finite_grid(g)) return XRT_EINVAL;
+    if (g.nx > kMaxGrid || g.ny > kMaxGrid) return XRT_ESIZE;
+    return XRT_OK;
+}
+
+xrt_status check_lines(const xrt_lines* L)
+{
+    if (!L) return XRT_EINVAL;
+    if (L->n < 0) return XRT_EINVAL;
+    if (L->n >= (int64_t)0x7fffffff) return XRT_ESIZE;
+    if (L->kind == XRT_LINES_THETA_Y) {
+        if (L->n > 0 && (!L->theta || !L->y)) return XRT_EINVAL;
+    } else if (L->kind == XRT_LINES_ENDPOINTS) {
+        if (L->n > 0 && !L->endpoints) return XRT_EINVAL;
+    } else {
+        return XRT_EINVAL;
+    }
+    return XRT_OK;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+struct Allocs {
+    hipStream_t s;
+    bool failed = false;
+    hipError_t err = hipSuccess;
+    template <class T>
+    T* get(size_t count)
+    {
+        if (failed) return nullptr;
+        void* p = nullptr;
+        size_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMallocAsync(&p, bytes, s);
+        if (e != hipSuccess) {
+            failed = true;
+            err = e;
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return (T*)p;
+    }
+};
+
+void free_plan_memory(xrt_plan* p, hipStream_t s)
+{
+    void* ptrs[] = {p->xc, p->kap, p->idx, p->off, p->hdr, p->tab,
+                    p->cv, p->dv, p->ch, p->dh, p->sw};
+    for (void* q : ptrs)
+        if (q) (void)hipFreeAsync(q, s);
+}
+
+}  // namespace
+
+namespace xrt {
+const float* etable_host(int n, int* n_entries)
+{
+    std::call_once(g_tab_once, build_tables);
+    if (n_entries) *n_entries = g_tab_n[n];
+    return g_tab[n];
+}
+}  // namespace xrt
+
+extern "C" {
+
+const char* xrt_version(void) { return "0.1.0"; }
+
+const char* xrt_status_string(xrt_status st)
+{
+    switch (st) {
+    case XRT_OK: return "ok";
+    case XRT_EINVAL: return "invalid argument";
+    case XRT_EDEGREE: return "degree must be 0, 1, 2 or 3";
+    case XRT_ESIZE: return "size out of the supported range";
+    case XRT_ENOMEM: return "device memory allocation failed";
+    case XRT_EHIP: return "HIP runtime error";
+    case XRT_EPLAN: return "invalid plan";
+    default: return "unknown status";
+    }
+}
+
+const char* xrt_last_error(void) { return g_last_error; }
+
+xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream,
+                           xrt_plan** out)
+{
+    if (!out) return XRT_EINVAL;
+    *out = nullptr;
+    if (degree < 0 || degree > 3) return XRT_EDEGREE;
+    xrt_status st = check_grid(g);
+    if (st != XRT_OK) return st;
+    st = check_lines(lines);
+    if (st != XRT_OK) return st;
+
+    hipStream_t s = (hipStream_t)stream;
+    xrt_plan* p = new (std::nothrow) xrt_plan;
+    if (!p) return XRT_ENOMEM;
+    memset(p, 0, sizeof(*p));
+    p->magic = kPlanMagic;
+    p->g.nx = g.nx;
+    p->g.ny = g.ny;
+    p->g.h = g.spacing;
+    p->g.cx = g.cx;
+    p->g.cy = g.cy;
+    p->degree = degree;
+    p->m = lines->n;
+    // crossing buckets: floor(Xc) + boff in [0, nbk) for every line that
+    // reaches the grid (|Xc| <= nmin + nmaj/2 + (n+1))
+    p->boff_v = (g.ny + 1) / 2 + 8;
+    p->boff_h = (g.nx + 1) / 2 + 8;
+    p->nbk_v = g.nx + g.ny + 24;
+    p->nbk_h = g.nx + g.ny + 24;
+    const int64_t per_v = (int64_t)kSlopeBins * p->nbk_v, per_h = (int64_t)kSlopeBins * p->nbk_h;
+    p->key_space = per_v + per_h + 1;
+    p->pitch_v = round_up(g.nx + 2 * kPad, 16);
+    p->pitch_h = round_up(g.ny + 2 * kPad, 16);
+
+    const int64_t m = p->m;
+    Allocs al{s};
+    p->xc = al.get<double>(m);
+    p->kap = al.get<double>(m);
+    p->idx = al.get<int32_t>(m);
+    p->off = al.get<uint32_t>(p->key_space + 1);
+    p->hdr = al.get<PlanHeader>(1);
+    p->tab = al.get<float4>(kTabMax);
+    p->cv = al.get<float>((size_t)g.ny * p->pitch_v);
+    p->dv = al.get<float>((size_t)g.ny * p->pitch_v);
+    p->ch = al.get<float>((size_t)g.nx * p->pitch_h);
+    p->dh = al.get<float>((size_t)g.nx * p->pitch_h);
+    p->sw = al.get<float>(m);
+    // temporaries
+    uint32_t* key = al.get<uint32_t>(m);
+    double* xc_in = al.get<double>(m);
+    double* kap_in = al.get<double>(m);
+    uint32_t* count = al.get<uint32_t>(p->key_space);
+    const int64_t scan_words = scan_tmp_words(p->key_space);
+    uint32_t* scan_tmp = al.get<uint32_t>(scan_words);
+    uint32_t* cursor = al.get<uint32_t>(p->key_space + 1);
+    auto free_tmp = [&]() {
+        void* t[] = {key, xc_in, kap_in, count, scan_tmp, cursor};
+        for (void* q : t)
+            if (q) (void)hipFreeAsync(q, s);
+    };
+    if (al.failed) {
+        set_error("hipMallocAsync", al.err);
+        free_tmp();
+        free_plan_memory(p, s);
+        (void)hipStreamSynchronize(s);
+        delete p;
+        return XRT_ENOMEM;
+    }
+
+    hipError_t e = hipSuccess;
+    const char* what = "plan";
+    int ntab = 0;
+    const float* tab = etable_host(degree, &ntab);
+#define XRT_TRY(call, label)                 \
+    do {                                     \
+        if (e == hipSuccess) {               \
+            e = (call);                      \
+            if (e != hipSuccess) what = label; \
+        }                                    \
+    } while (0)
+    XRT_TRY(hipMemcpyAsync(p->tab, tab, sizeof(float) * 4 * ntab, hipMemcpyHostToDevice, s),
+            "table upload");
+    XRT_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t) * p->key_space, s), "memset");
+    XRT_TRY(hipMemsetAsync(p->hdr, 0, sizeof(PlanHeader), s), "memset");
+    CanonArgs ca;
+    ca.L.kind = lines->kind;
+    ca.L.theta = lines->theta;
+    ca.L.y = lines->y;
+    ca.L.ep = lines->endpoints;
+    ca.m = m;
+    ca.g = p->g;
+    ca.degree = degree;
+    ca.nbk_v = p->nbk_v;
+    ca.nbk_h = p->nbk_h;
+    ca.boff_v = p->boff_v;
+    ca.boff_h = p->boff_h;
+    ca.key = key;
+    ca.xc = xc_in;
+    ca.kap = kap_in;
+    ca.count = count;
+    ca.hdr = p->hdr;
+    XRT_TRY(launch_canon(ca, s), "canonicalize");
+    XRT_TRY(launch_scan(count, p->off, p->key_space, scan_tmp, s), "scan");
+    XRT_TRY(hipMemcpyAsync(cursor, p->off, sizeof(uint32_t) * p->key_space,
+                           hipMemcpyDeviceToDevice, s),
+            "copy");
+    ScatterArgs sa;
+    sa.m = m;
+    sa.key = key;
+    sa.xc_in = xc_in;
+    sa.kap_in = kap_in;
+    sa.cursor = cursor;
+    sa.xc = p->xc;
+    sa.kap = p->kap;
+    sa.idx = p->idx;
+    XRT_TRY(launch_scatter(sa, s), "scatter");
+    XRT_TRY(launch_header(p->hdr, p->off, per_v, per_v + per_h, s), "header");
+    PlanHeader h;
+    memset(&h, 0, sizeof(h));
+    XRT_TRY(hipMemcpyAsync(&h, p->hdr, sizeof(h), hipMemcpyDeviceToHost, s), "header read");
+    free_tmp();
+    XRT_TRY(hipStreamSynchronize(s), "synchronize");
+#undef XRT_TRY
+    if (e != hipSuccess) {
+        set_error(what, e);
+        free_plan_memory(p, s);
+        (void)hipStreamSynchronize(s);
+        delete p;
+        return XRT_EHIP;
+    }
+    if (h.error) {
+        free_plan_memory(p, s);
+        (void)hipStreamSynchronize(s);
+        delete p;
+        return XRT_EINVAL;
+    }
+    p->m_vert = h.m_vert;
+    p->m_valid = h.m_valid;
+    *out = p;
+    return XRT_OK;
+}
+
+static bool plan_ok(const xrt_plan* p) { return p && p->magic == kPlanMagic; }
+
+xrt_status xrt_plan_info(const xrt_plan* p, int64_t* n_lines, int64_t* n_crossing)
+{
+    if (!plan_ok(p)) return XRT_EPLAN;
+    if (n_lines) *n_lines = p->m;
+    if (n_crossing) *n_crossing = p->m_valid;
+    return XRT_OK;
+}
+
+xrt_status xrt_plan_forward(const xrt_plan* p, const float* coeffs, float* sino, void* stream)
+{
+    if (!plan_ok(p)) return XRT_EPLAN;
+    if (!coeffs || (!sino && p->m > 0)) return XRT_EINVAL;
+    hipError_t e = launch_forward(p, coeffs, sino, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("forward launch", e);
+        return XRT_EHIP;
+    }
+    return XRT_OK;
+}
+
+xrt_status xrt_plan_adjoint(const xrt_plan* p, const float* sino, float* coeffs_out, void* stream)
+{
+    if (!plan_ok(p)) return XRT_EPLAN;
+    if (!coeffs_out || (!sino && p->m > 0)) return XRT_EINVAL;
+    hipError_t e = launch_adjoint(p, sino, coeffs_out, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_error("adjoint launch", e);
+        return XRT_EHIP;
+    }
+    return XRT_OK;
+}
+
+xrt_status xrt_plan_nnz(const xrt_plan* p, int64_t* nnz, void* stream)
+{
+    if (!plan_ok(p)) return XRT_EPLAN;
+    if (!nnz) return XRT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* d = nullptr;
+    hipError_t e = hipMallocAsync((void**)&d, sizeof(*d), s);
+    if (e != hipSuccess) {
+        set_error("hipMallocAsync", e);
+        return XRT_ENOMEM;
+    }
+    unsigned long long hcount = 0;
+    e = hipMemsetAsync(d, 0, sizeof(*d), s);
+    if (e == hipSuccess) e = launch_nnz(p, d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hcount, d, sizeof(hcount), hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(d, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) {
+        set_error("nnz", e);
+        return XRT_EHIP;
+    }
+    *nnz = (int64_t)hcount;
+    return XRT_OK;
+}
+
+void xrt_plan_destroy(xrt_plan* p)
+{
+    if (!plan_ok(p)) return;
+    (void)hipDeviceSynchronize();
+    free_plan_memory(p, nullptr);
+    (void)hipDeviceSynchronize();
+    p->magic = 0;
+    delete p;
+}
+
+xrt_status xrt_forward(const float* coeffs, xrt_grid g, int degree, const xrt_lines* lines,
+                       float* sino, void* stream)
+{
+    if (!coeffs || !lines) return XRT_EINVAL;
+    if (degree < 0 || degree > 3) return XRT_EDEGREE;
+    xrt_status st = check_grid(g);
+    if (st != XRT_OK) return st;
+    st = check_lines(lines);
+    if (st != XRT_OK) return st;
+    if (lines->n > 0 && !sino) return XRT_EINVAL;
+    xrt_plan* p = nullptr;
+    st = xrt_plan_create(g, degree, lines, stream, &p);
+    if (st != XRT_OK) return st;
+    st = xrt_plan_forward(p, coeffs, sino, stream);
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipStreamSynchronize(s);
+    free_plan_memory(p, s);
+    (void)hipStreamSynchronize(s);
+    p->magic = 0;
+    delete p;
+    return st;
+}
+
+xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xrt_grid g,
+                       float* coeffs_out, void* stream)
+{
+    if (!coeffs_out || !lines) return XRT_EINVAL;
+    if (degree < 0 || degree > 3) return XRT_EDEGREE;
+    xrt_status st = check_grid(g);
+    if (st != XRT_OK) return st;
+    st = check_lines(lines);
+    if (st != XRT_OK) return st;
+    if (lines->n > 0 && !sino) return XRT_EINVAL;
+    xrt_plan* p = nullptr;
+    st = xrt_plan_create(g, degree, lines, stream, &p);
+    if (st != XRT_OK) return st;
+    st = xrt_plan_adjoint(p, sino, coeffs_out, stream);
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipStreamSynchronize(s);
+    free_plan_memory(p, s);
+    (void)hipStreamSynchronize(s);
+    p->magic = 0;
+    delete p;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal definitions shared by the translation units of libxrt.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xrt.h"
+
+namespace xrt {
+
+// Padding (in cells) on both sides of every row of the coefficient layouts;
+// large enough for every tap and knot slot a line touches in a row it visits.
+constexpr int kPad = 8;
+// Slope bins of the plan (the slope kappa of a line lies in [-1, 1]).
+constexpr int kSlopeBins = 512;
+// Intervals per unit of the knot-transition table.
+constexpr int kTabPerUnit = 64;
+// Largest table: degree 3, half-support 2 -> 128 intervals + 1 zero interval.
+constexpr int kTabMax = kTabPerUnit * 2 + 1;
+// Adjoint tile (pixels): kTileI columns (x1) by kTileJ rows (x2).
+constexpr int kTileI = 64;
+constexpr int kTileJ = 64;
+// Halo (cells) of the LDS accumulators of the adjoint on each minor side.
+constexpr int kHalo = 10;
+constexpr int kBlock = 256;
+
+// Number of knot-transition slots per row for degree n.
+__host__ __device__ constexpr int n_slots(int n) { return n + 1; }
+
+// Device-resident plan header, written by the plan builder.
+struct PlanHeader {
+    int64_t m_vert;   // sorted lines [0, m_vert) are "vertical" (|sin| >= |cos|)
+    int64_t m_valid;  // sorted lines [m_vert, m_valid) are "horizontal"; the rest miss the grid
+    int64_t error;    // non-zero: a line was degenerate or non-finite
+    int64_t pad;
+};
+
+struct GridGeom {
+    int nx, ny;
+    double h, cx, cy;
+};
+
+
+struct LineIn {
+    int kind;
+    const float* theta;
+    const float* y;
+    const float* ep;
+};
+
+struct CanonArgs {
+    LineIn L;
+    int64_t m;
+    GridGeom g;
+    int degree;
+    int nbk_v, nbk_h, boff_v, boff_h;
+    uint32_t* key;
+    double* xc;
+    double* kap;
+    uint32_t* count;  // [key_space]
+    xrt::PlanHeader* hdr;
+};
+
+struct ScatterArgs {
+    int64_t m;
+    const uint32_t* key;
+    const double* xc_in;
+    const double* kap_in;
+    uint32_t* cursor;
+    double* xc;
+    double* kap;
+    int32_t* idx;
+};
+
+// Launchers (xrt_kernels.hip).  All enqueue on `s` and return the launch status.
+hipError_t launch_canon(const CanonArgs& a, hipStream_t s);
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
+int64_t scan_tmp_words(int64_t n);
+hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
+hipError_t launch_header(PlanHeader* hdr, const uint32_t* off, int64_t vert_end, int64_t valid_end,
+                         hipStream_t s);
+hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, hipStream_t s);
+hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s);
+hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s);
+// Knot-transition table of degree n (host, FP64-built, rounded to float):
+// kTabPerUnit*(n+1)/2 cubic intervals plus one zero interval, 4 floats each.
+const float* etable_host(int n, int* n_entries);
+
+}  // namespace xrt
+
+struct xrt_plan;
+struct xrt_plan {
+    uint64_t magic;
+    xrt::GridGeom g;
+    int degree;
+    int64_t m;          // number of lines
+    int64_t m_vert, m_valid;
+    int nbk_v, nbk_h;   // crossing buckets per slope bin, per orientation
+    int boff_v, boff_h; // bucket offset, per orientation
+    int64_t key_space;  // number of keys (2 * bins * buckets + 1)
+    // sorted line records
+    double* xc;         // crossing of the centre major line
+    double* kap;        // slope d(minor)/d(major)
+    int32_t* idx;       // original position of the line
+    uint32_t* off;      // [key_space + 1] start of every key in sorted order
+    xrt::PlanHeader* hdr;
+    float4* tab;        // knot-transition table of this degree
+    // workspace
+    int pitch_v, pitch_h;
+    float *cv, *dv, *ch, *dh;  // coefficient / difference layouts
+    float* sw;                 // sinogram in sorted order, scaled
+};

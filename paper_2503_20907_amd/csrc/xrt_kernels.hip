@@ -1,0 +1,894 @@
+// HIP kernels of libxrt.so (gfx950): plan building, coefficient layouts,
+// forward projection and tile-binned adjoint of the B-spline x-ray transform.
+//
+// The footprint of a line with |sin t| >= |cos t| ("vertical"; the other case
+// swaps x1 and x2, the case split of Section II-B) is evaluated row by row.
+// In row j the line crosses the row's centre line at minor coordinate
+// X(j) = X0 + kappa j (kappa = cot t), and the row contributes
+//     (h/|sin t|) sum_i c_ij psi_r(X(j) - i),   r = |kappa| <= 1,
+// where psi_r = beta^n * beta^n_r is the footprint of Proposition 1 / eq. (6)
+// written in units of the row (phi_theta(u) = psi_r(u/|sin t|)/|sin t|).
+//
+// psi_r is split exactly (derived from eq. (6), see the design notes) as
+//     psi_r(v) = S_r(v) + sum_k delta_k r^n E((v - kappa_k)/r),
+//     S_r = beta^n + [n >= 2] r^2 (mu_2/2) beta^n'',
+//     delta_k = (-1)^k C(n+1, k),  kappa_k = k - (n+1)/2 (knots of beta^n),
+// where mu_2 = (n+1)/12 is the second moment of beta^n and E is one fixed
+// function of compact support (-(n+1)/2, (n+1)/2) per degree (the (n+1)-fold
+// integral of beta^n minus its polynomial tail).  Summed over a row this gives
+//     sum_i c_i psi_r(X - i) = sum_d W_d(t) c_{J-d}
+//                            + r^n sum_K E((X + (n+1)/2 - K)/r) D_K,
+// with J = floor(X + (n+1)/2), t its fraction, W_d the n+1 B-spline weights
+// (plus the r^2 beta'' term), and D_K = sum_l delta_l c_{K-l} the (n+1)-th
+// backward difference of the row at knot K.  At most n+1 knots K lie within
+// (n+1) r / 2 of X, so a row costs n+1 taps plus n+1 knot slots whatever r
+// is.  E is held in LDS as a cubic-per-interval table (64 intervals per unit)
+// built in FP64 on the host.  Line geometry (crossings, floors) is FP64; the
+// row arithmetic is FP32 in local coordinates t in [0, 1).
+//
+// The adjoint applies the transpose of exactly the same row arithmetic:
+// every line adds W_d s to the cells J-d and r^n E(.) s to the knots K of an
+// LDS tile, and the tile's output is A + Delta^T K, written once.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "xrt_internal.h"
+
+namespace xrt {
+
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+
+// ---------------------------------------------------------------- geometry
+struct Canon {
+    double xc;   // crossing at the centre major index
+    double kap;  // slope
+    int cls;     // 0 vertical, 1 horizontal, 2 misses the padded grid
+    int bad;     // degenerate / non-finite input
+};
+
+
+// Line (theta, y) of eq. (1) in world coordinates -> index space of the grid,
+// then to the crossing form minor = X0 + kappa * major.
+__device__ inline Canon canonicalize(const LineIn& L, int64_t m, const GridGeom& g, int degree)
+{
+    Canon o;
+    o.bad = 0;
+    double c, s, yw;
+    if (L.kind == XRT_LINES_ENDPOINTS) {
+        double px = L.ep[4 * m + 0], py = L.ep[4 * m + 1];
+        double qx = L.ep[4 * m + 2], qy = L.ep[4 * m + 3];
+        double dx = qx - px, dy = qy - py;
+        double len = sqrt(dx * dx + dy * dy);
+        if (!(len > 0.0) || !isfinite(len) || !isfinite(px) || !isfinite(py)) {
+            o.bad = 1;
+            len = 1.0;
+            dx = 1.0;
+            dy = 0.0;
+        }
+        c = dx / len;
+        s = dy / len;
+        yw = px * s - py * c;
+    } else {
+        double t = (double)L.theta[m];
+        yw = (double)L.y[m];
+        if (!isfinite(t) || !isfinite(yw)) {
+            o.bad = 1;
+            t = 0.0;
+            yw = 0.0;
+        }
+        sincos(t, &s, &c);
+    }
+    // i*s - j*c = Y in index space
+    const double ox = 0.5 * (g.nx - 1), oy = 0.5 * (g.ny - 1);
+    const double Y = (yw - (g.cx * s - g.cy * c)) / g.h + ox * s - oy * c;
+    const bool vert = fabs(s) >= fabs(c);
+    const int nmaj = vert ? g.ny : g.nx, nmin = vert ? g.nx : g.ny;
+    double X0, kap;
+    if (vert) {
+        X0 = Y / s;
+        kap = c / s;
+    } else {
+        X0 = -Y / c;
+        kap = s / c;
+    }
+    const double jc = 0.5 * (nmaj - 1);
+    o.xc = X0 + kap * jc;
+    o.kap = kap;
+    // rows whose band reaches the grid: -W < X(j) < nmin - 1 + W
+    const double W = 0.5 * (degree + 1) * (1.0 + fabs(kap));
+    bool hit;
+    if (kap == 0.0) {
+        hit = X0 > -W && X0 < nmin - 1 + W;
+    } else {
+        double a = (-W - X0) / kap, b = (nmin - 1 + W - X0) / kap;
+        double lo = fmin(a, b), hi = fmax(a, b);
+        hit = hi > 0.0 && lo < (double)(nmaj - 1);
+    }
+    o.cls = o.bad ? 2 : (hit ? (vert ? 0 : 1) : 2);
+    return o;
+}
+
+// Rows [jlo, jhi] (closed) of a line whose band may reach the grid.
+__device__ inline void row_range(double x0, double kap, double W, int nmaj, int nmin, int* jlo,
+                                 int* jhi)
+{
+    if (kap == 0.0) {
+        *jlo = 0;
+        *jhi = nmaj - 1;
+        return;
+    }
+    double a = (-W - x0) / kap, b = (nmin - 1 + W - x0) / kap;
+    double lo = fmin(a, b), hi = fmax(a, b);
+    double flo = ceil(lo - 1e-9), fhi = floor(hi + 1e-9);
+    *jlo = (int)fmax(0.0, flo);
+    *jhi = (int)fmin((double)(nmaj - 1), fhi);
+}
+
+__device__ inline int slope_bin(double kap)
+{
+    int b = (int)floor((kap + 1.0) * (0.5 * kSlopeBins));
+    return b < 0 ? 0 : (b >= kSlopeBins ? kSlopeBins - 1 : b);
+}
+
+// ---------------------------------------------------------------- plan build
+
+__global__ void __launch_bounds__(kBlock) k_canon(CanonArgs A)
+{
+    int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (m >= A.m) return;
+    Canon o = canonicalize(A.L, m, A.g, A.degree);
+    uint32_t key;
+    const uint32_t per_cls_v = (uint32_t)kSlopeBins * (uint32_t)A.nbk_v;
+    const uint32_t per_cls_h = (uint32_t)kSlopeBins * (uint32_t)A.nbk_h;
+    if (o.cls == 2) {
+        key = per_cls_v + per_cls_h;
+    } else {
+        const int nbk = o.cls == 0 ? A.nbk_v : A.nbk_h;
+        const int boff = o.cls == 0 ? A.boff_v : A.boff_h;
+        double fb = floor(o.xc) + boff;
+        int bk = (int)fmin(fmax(fb, 0.0), (double)(nbk - 1));
+        key = (o.cls == 0 ? 0u : per_cls_v) + (uint32_t)slope_bin(o.kap) * (uint32_t)nbk + (uint32_t)bk;
+    }
+    if (o.bad) atomicOr((unsigned long long*)&A.hdr->error, 1ull);
+    A.key[m] = key;
+    A.xc[m] = o.xc;
+    A.kap[m] = o.kap;
+    atomicAdd(&A.count[key], 1u);
+}
+
+// Exclusive scan of n uint32 (block-local part): every block scans
+// kBlock * 8 elements and writes its total to part[blockIdx.x].
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total)
+{
+    // Hillis-Steele over the block in LDS
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+        uint32_t x = tid >= d ? sh[tid - d] : 0u;
+        __syncthreads();
+        sh[tid] += x;
+        __syncthreads();
+    }
+    uint32_t incl = sh[tid];
+    *total = sh[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_tile(const uint32_t* in, uint32_t* out,
+                                                    uint32_t* part, int64_t n)
+{
+    __shared__ uint32_t sh[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+        v[e] = base + e < n ? in[base + e] : 0u;
+        sum += v[e];
+    }
+    uint32_t total;
+    uint32_t pre = block_excl_scan(sum, sh, &total);
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+        if (base + e < n) out[base + e] = pre;
+        pre += v[e];
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_add(uint32_t* out, const uint32_t* part, int64_t n)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const uint32_t add = part[blockIdx.x];
+    for (int e = threadIdx.x; e < kScanTile; e += kBlock) {
+        int64_t i = base + e;
+        if (i < n) out[i] += add;
+    }
+}
+
+
+__global__ void __launch_bounds__(kBlock) k_scatter(ScatterArgs A)
+{
+    int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (m >= A.m) return;
+    uint32_t pos = atomicAdd(&A.cursor[A.key[m]], 1u);
+    A.xc[pos] = A.xc_in[m];
+    A.kap[pos] = A.kap_in[m];
+    A.idx[pos] = (int32_t)m;
+}
+
+__global__ void k_header(PlanHeader* hdr, const uint32_t* off, int64_t vert_end, int64_t valid_end)
+{
+    hdr->m_vert = off[vert_end];
+    hdr->m_valid = off[valid_end];
+}
+
+// ---------------------------------------------------------------- layouts
+// Backward (n+1)-th difference weights delta_l = (-1)^l C(n+1, l).
+template <int N>
+__device__ inline float delta_w(int l)
+{
+    constexpr float d0[2] = {1.f, -1.f};
+    constexpr float d1[3] = {1.f, -2.f, 1.f};
+    constexpr float d2[4] = {1.f, -3.f, 3.f, -1.f};
+    constexpr float d3[5] = {1.f, -4.f, 6.f, -4.f, 1.f};
+    return N == 0 ? d0[l] : N == 1 ? d1[l] : N == 2 ? d2[l] : d3[l];
+}
+
+// Rows of C along x1 (for vertical lines): cv[j][p] = c[j][p - kPad],
+// dv[j][p] = sum_l delta_l c[j][p - kPad - l] (zero outside the grid).
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_layout_v(const float* __restrict__ c, int nx, int ny,
+                                                     int pitch, float* __restrict__ cv,
+                                                     float* __restrict__ dv)
+{
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blockIdx.y;
+    if (p >= pitch) return;
+    const float* row = c + (int64_t)j * nx;
+    const int i = p - kPad;
+    float cc = (i >= 0 && i < nx) ? row[i] : 0.f;
+    float d = 0.f;
+#pragma unroll
+    for (int l = 0; l <= N + 1; ++l) {
+        int ii = i - l;
+        float v = (ii >= 0 && ii < nx) ? row[ii] : 0.f;
+        d += delta_w<N>(l) * v;
+    }
+    cv[(int64_t)j * pitch + p] = cc;
+    dv[(int64_t)j * pitch + p] = d;
+}
+
+// Columns of C (for horizontal lines), transposed through LDS:
+// ch[i][p] = c[p - kPad][i], dh[i][p] = sum_l delta_l c[p - kPad - l][i].
+constexpr int kTr = 32;
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_layout_h(const float* __restrict__ c, int nx, int ny,
+                                                     int pitch, float* __restrict__ ch,
+                                                     float* __restrict__ dh)
+{
+    __shared__ float sh[kTr + 4][kTr + 1];
+    const int p0 = blockIdx.x * kTr;  // padded position along x2 (output minor)
+    const int i0 = blockIdx.y * kTr;  // column index (output major)
+    const int tx = threadIdx.x % kTr, ty = threadIdx.x / kTr;  // 32 x 8
+    // rows j = p0 - kPad - (N+1) + r for r in [0, kTr + N + 1)
+    for (int r = ty; r < kTr + N + 1; r += kBlock / kTr) {
+        int j = p0 - kPad - (N + 1) + r;
+        int i = i0 + tx;
+        sh[r][tx] = (j >= 0 && j < ny && i < nx) ? c[(int64_t)j * nx + i] : 0.f;
+    }
+    __syncthreads();
+    for (int r = ty; r < kTr; r += kBlock / kTr) {
+        int i = i0 + r;      // output row (major)
+        int p = p0 + tx;     // output position
+        if (i >= nx || p >= pitch) continue;
+        float cc = sh[tx + N + 1][r];
+        float d = 0.f;
+#pragma unroll
+        for (int l = 0; l <= N + 1; ++l) d += delta_w<N>(l) * sh[tx + N + 1 - l][r];
+        ch[(int64_t)i * pitch + p] = cc;
+        dh[(int64_t)i * pitch + p] = d;
+    }
+}
+
+// ---------------------------------------------------------------- row math
+// Constants of one line: r = |kappa|, 1/r, r^n, the beta'' weight rho.
+struct LineConst {
+    float inv_r, rn, rho;
+};
+
+template <int N>
+__device__ inline LineConst line_const(double kap)
+{
+    LineConst k;
+    float r = (float)fabs(kap);
+    k.inv_r = 1.0f / fmaxf(r, 1e-30f);
+    float rn = 1.f;
+#pragma unroll
+    for (int e = 0; e < N; ++e) rn *= r;
+    k.rn = rn;
+    // (r^2/2) * mu_2 with mu_2 = (n+1)/12; the term exists for n >= 2
+    k.rho = N >= 2 ? r * r * (float)(N + 1) / 24.0f : 0.f;
+    return k;
+}
+
+// Knot-transition table lookup: g(|z|) with the parity of E.
+template <int N>
+__device__ inline float etab(const float4* __restrict__ tab, float z)
+{
+    constexpr float last = (float)(kTabPerUnit * (N + 1)) * 0.5f;  // index of the zero interval
+    float a = fabsf(z) * (float)kTabPerUnit;
+    a = fminf(a, last);
+    int i = (int)a;
+    float tau = a - (float)i;
+    float4 cf = tab[i];
+    float g = fmaf(tau, fmaf(tau, fmaf(tau, cf.w, cf.z), cf.y), cf.x);
+    if constexpr (N % 2 == 0) g = z >= 0.f ? -g : g;
+    return g;
+}
+
+// Everything one row needs: tap base J (taps J-d, d = 0..N) with weights w[d],
+// knot base K0 (slots K0 + s) with values e[s] (already times r^n).
+template <int N>
+struct RowTaps {
+    int J, K0;
+    float w[N + 1];
+    float e[N + 1];
+};
+
+template <int N>
+__device__ inline void row_taps(double q, const LineConst& k, const float4* __restrict__ tab,
+                                RowTaps<N>& R)
+{
+    // q = X + (n+1)/2; taps J - d carry beta^n(t + d - (n+1)/2) (+ rho beta'').
+    const double Jd = floor(q);
+    const float t = (float)(q - Jd);
+    R.J = (int)Jd;
+    if constexpr (N == 0) {
+        R.w[0] = 1.f;
+    } else if constexpr (N == 1) {
+        R.w[0] = t;
+        R.w[1] = 1.f - t;
+    } else if constexpr (N == 2) {
+        const float u = t - 0.5f, s = 1.f - t;
+        R.w[0] = 0.5f * t * t + k.rho;
+        R.w[1] = 0.75f - u * u - 2.f * k.rho;
+        R.w[2] = 0.5f * s * s + k.rho;
+    } else {
+        const float t2 = t * t, t3 = t2 * t, s = 1.f - t;
+        const float s3 = s * s * s;
+        const float r6 = 1.f / 6.f;
+        R.w[0] = t3 * r6 + k.rho * t;
+        R.w[3] = s3 * r6 + k.rho * s;
+        R.w[2] = fmaf(3.f * t3 - 6.f * t2 + 4.f, r6, k.rho * (3.f * t - 2.f));
+        R.w[1] = fmaf(-3.f * t3 + 3.f * t2 + 3.f * t + 1.f, r6, k.rho * (1.f - 3.f * t));
+    }
+    // knot slots: odd n use J, even n the nearest integer to q
+    if constexpr (N % 2 == 1) {
+        R.K0 = R.J - (N - 1) / 2;
+#pragma unroll
+        for (int sl = 0; sl <= N; ++sl) {
+            // z = (q - K)/r with K = K0 + sl:  q - K = t + (N-1)/2 - sl
+            float z = (t + (float)((N - 1) / 2 - sl)) * k.inv_r;
+            R.e[sl] = etab<N>(tab, z) * k.rn;
+        }
+    } else {
+        const double J2 = floor(q + 0.5);
+        const float t2 = (float)(q + 0.5 - J2);
+        R.K0 = (int)J2 - N / 2;
+#pragma unroll
+        for (int sl = 0; sl <= N; ++sl) {
+            // q - K = t2 - 0.5 + N/2 - sl
+            float z = (t2 + (float)(N / 2 - sl) - 0.5f) * k.inv_r;
+            R.e[sl] = etab<N>(tab, z) * k.rn;
+        }
+    }
+}
+
+// Loads of N+1 consecutive floats (pointer at the first).
+template <int N>
+__device__ inline void load_taps(const float* __restrict__ p, float* v)
+{
+    if constexpr (N == 0) {
+        v[0] = p[0];
+    } else if constexpr (N == 1) {
+        f2u a = *(const f2u*)p;
+        v[0] = a.x;
+        v[1] = a.y;
+    } else {
+        f4u a = *(const f4u*)p;
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = a.z;
+        if constexpr (N == 3) v[3] = a.w;
+    }
+}
+
+__device__ inline int xcd_logical(int bid, int nblk_pad)
+{
+    // blocks are dispatched round-robin over the 8 XCDs; give every XCD one
+    // contiguous range of logical blocks so that its L2 sees neighbouring work
+    const int per = nblk_pad / 8;
+    return (bid % 8) * per + bid / 8;
+}
+
+// ---------------------------------------------------------------- forward
+struct FwdArgs {
+    int64_t m;
+    const PlanHeader* hdr;
+    const double* xc;
+    const double* kap;
+    const int32_t* idx;
+    const float4* tab;
+    const float* cv;
+    const float* dv;
+    const float* ch;
+    const float* dh;
+    int pitch_v, pitch_h;
+    int nx, ny;
+    double h;
+    float* sino;
+    int nblk, nblk_pad;
+};
+
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
+{
+    __shared__ float4 s_tab[kTabMax];
+    const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
+    for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
+    __syncthreads();
+
+    const int lb = xcd_logical(blockIdx.x, A.nblk_pad);
+    if (lb >= A.nblk) return;
+    const int64_t k = (int64_t)lb * kBlock + threadIdx.x;
+    if (k >= A.m) return;
+    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
+    const int out = A.idx[k];
+    if (k >= m_valid) {
+        A.sino[out] = 0.f;
+        return;
+    }
+    const bool vert = k < m_vert;
+    const double xc = A.xc[k], kap = A.kap[k];
+    const int nmaj = vert ? A.ny : A.nx, nmin = vert ? A.nx : A.ny;
+    const int pitch = vert ? A.pitch_v : A.pitch_h;
+    const float* __restrict__ C = vert ? A.cv : A.ch;
+    const float* __restrict__ D = vert ? A.dv : A.dh;
+    const double H = 0.5 * (N + 1);
+    const double x0 = xc - kap * (0.5 * (nmaj - 1));
+    int jlo, jhi;
+    row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+    const LineConst lc = line_const<N>(kap);
+    const double q0 = x0 + kap * (double)jlo + H;
+    double acc = 0.0;
+    for (int j = jlo; j <= jhi; ++j) {
+        const double q = fma(kap, (double)(j - jlo), q0);
+        RowTaps<N> R;
+        row_taps<N>(q, lc, s_tab, R);
+        const float* crow = C + (int64_t)j * pitch + kPad;
+        float cvv[N + 1], dvv[N + 1];
+        load_taps<N>(crow + (R.J - N), cvv);  // c_{J-N} .. c_J
+        load_taps<N>(D + (int64_t)j * pitch + kPad + R.K0, dvv);
+        float row = 0.f;
+#pragma unroll
+        for (int d = 0; d <= N; ++d) row = fmaf(R.w[d], cvv[N - d], row);
+#pragma unroll
+        for (int sl = 0; sl <= N; ++sl) row = fmaf(R.e[sl], dvv[sl], row);
+        acc += (double)row;
+    }
+    const double scale = A.h * sqrt(1.0 + kap * kap);
+    A.sino[out] = (float)(acc * scale);
+}
+
+// ---------------------------------------------------------------- adjoint
+// Sinogram in sorted order, times h / max(|cos|, |sin|).
+struct SortSinoArgs {
+    int64_t m;
+    const PlanHeader* hdr;
+    const double* kap;
+    const int32_t* idx;
+    const float* sino;
+    double h;
+    float* sw;
+};
+
+__global__ void __launch_bounds__(kBlock) k_sort_sino(SortSinoArgs A)
+{
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= A.m) return;
+    if (k >= A.hdr->m_valid) {
+        A.sw[k] = 0.f;
+        return;
+    }
+    double kap = A.kap[k];
+    A.sw[k] = (float)((double)A.sino[A.idx[k]] * A.h * sqrt(1.0 + kap * kap));
+}
+
+struct AdjArgs {
+    const double* xc;
+    const double* kap;
+    const float* sw;
+    const uint32_t* off;
+    const float4* tab;
+    int nx, ny;
+    int nbk_v, nbk_h, boff_v, boff_h;
+    int tiles_i, tiles_j;
+    int ntiles, ntiles_pad;
+    float* out;
+};
+
+constexpr int kAccW = (kTileI > kTileJ ? kTileI : kTileJ) + 2 * kHalo;
+constexpr int kAccRows = kTileI > kTileJ ? kTileI : kTileJ;
+constexpr int kPix = kTileI * kTileJ / kBlock;
+
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_adjoint(AdjArgs A)
+{
+    __shared__ float s_a[kAccRows * kAccW];
+    __shared__ float s_k[kAccRows * kAccW];
+    __shared__ float4 s_tab[kTabMax];
+    __shared__ uint32_t s_start[kSlopeBins];
+    __shared__ uint32_t s_pre[kSlopeBins + 1];
+    __shared__ uint32_t s_scan[kBlock];
+
+    const int tid = threadIdx.x;
+    const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
+    for (int e = tid; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
+
+    const int tile = xcd_logical(blockIdx.x, A.ntiles_pad);
+    if (tile >= A.ntiles) return;  // uniform per block
+    const int ti = tile % A.tiles_i, tj = tile / A.tiles_i;
+    const int i0 = ti * kTileI, j0 = tj * kTileJ;
+    const double H = 0.5 * (N + 1);
+    const double marg = (double)N + 2.5;
+
+    float o[kPix];
+#pragma unroll
+    for (int e = 0; e < kPix; ++e) o[e] = 0.f;
+
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool vert = pass == 0;
+        // tile in (major, minor) coordinates of this orientation
+        const int maj0 = vert ? j0 : i0, min0 = vert ? i0 : j0;
+        const int TM = vert ? kTileJ : kTileI, TN = vert ? kTileI : kTileJ;
+        const int nmaj = vert ? A.ny : A.nx;
+        const int W = TN + 2 * kHalo;
+        const int nbk = vert ? A.nbk_v : A.nbk_h;
+        const int boff = vert ? A.boff_v : A.boff_h;
+        const uint32_t cls_base = vert ? 0u : (uint32_t)kSlopeBins * (uint32_t)A.nbk_v;
+        const double jc = 0.5 * (nmaj - 1);
+
+        for (int e = tid; e < TM * W; e += kBlock) {
+            s_a[e] = 0.f;
+            s_k[e] = 0.f;
+        }
+        // candidate range of every slope bin: lines whose crossing of some
+        // tile row falls within [min0 - marg, min0 + TN - 1 + marg]
+        uint32_t cnt_local[kSlopeBins / kBlock];
+#pragma unroll
+        for (int u = 0; u < kSlopeBins / kBlock; ++u) {
+            const int b = tid + u * kBlock;
+            const double klo = -1.0 + 2.0 * b / kSlopeBins, khi = -1.0 + 2.0 * (b + 1) / kSlopeBins;
+            const double da = maj0 - jc, db = maj0 + TM - 1 - jc;
+            const double e1 = klo * da, e2 = klo * db, e3 = khi * da, e4 = khi * db;
+            const double mx = fmax(fmax(e1, e2), fmax(e3, e4));
+            const double mn = fmin(fmin(e1, e2), fmin(e3, e4));
+            const double xlo = min0 - marg - mx, xhi = min0 + TN - 1 + marg - mn;
+            int blo = (int)fmin(fmax(floor(xlo) + boff, 0.0), (double)(nbk - 1));
+            int bhi = (int)fmin(fmax(floor(xhi) + boff, 0.0), (double)(nbk - 1));
+            const uint32_t base = cls_base + (uint32_t)b * (uint32_t)nbk;
+            const uint32_t st = A.off[base + blo], en = A.off[base + bhi + 1];
+            s_start[b] = st;
+            cnt_local[u] = en - st;
+        }
+        // exclusive scan of the counts (bins tid and tid + kBlock)
+        {
+            uint32_t c0 = cnt_local[0], c1 = cnt_local[1];
+            uint32_t tot;
+            // bins are laid out b = tid + u*kBlock: scan u-major
+            uint32_t p0 = block_excl_scan(c0, s_scan, &tot);
+            uint32_t tot0 = tot;
+            uint32_t p1 = block_excl_scan(c1, s_scan, &tot);
+            s_pre[tid] = p0;
+            s_pre[tid + kBlock] = tot0 + p1;
+            if (tid == 0) s_pre[kSlopeBins] = tot0 + tot;
+        }
+        __syncthreads();
+        const uint32_t total = s_pre[kSlopeBins];
+
+        for (uint32_t base = 0; base < total; base += kBlock) {
+            const uint32_t item = base + tid;
+            if (item < total) {
+                // bin b with s_pre[b] <= item < s_pre[b+1]
+                int lo = 0, hi = kSlopeBins;
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (s_pre[mid] <= item) lo = mid;
+                    else hi = mid;
+                }
+                const uint32_t k = s_start[lo] + (item - s_pre[lo]);
+                const double xc = A.xc[k], kap = A.kap[k];
+                const float sv = A.sw[k];
+                const double x0 = xc - kap * jc;
+                const int nmin = vert ? A.nx : A.ny;
+                int jlo, jhi;
+                row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+                // restrict to tile rows where the crossing is within the window
+                int ra = max(jlo, maj0), rb = min(jhi, maj0 + TM - 1);
+                if (kap != 0.0) {
+                    double a = (min0 - marg - x0) / kap, b = (min0 + TN - 1 + marg - x0) / kap;
+                    double lo2 = fmin(a, b), hi2 = fmax(a, b);
+                    ra = max(ra, (int)fmax(ceil(lo2 - 1e-9), -1.0e9));
+                    rb = min(rb, (int)fmin(floor(hi2 + 1e-9), 1.0e9));
+                } else if (!(x0 >= min0 - marg && x0 <= min0 + TN - 1 + marg)) {
+                    rb = ra - 1;
+                }
+                if (sv != 0.f && ra <= rb) {
+                    const LineConst lc = line_const<N>(kap);
+                    // local q: column index within the LDS row (halo included)
+                    const double q0 = x0 + kap * (double)ra + H - (double)min0 + (double)kHalo;
+                    for (int j = ra; j <= rb; ++j) {
+                        const double q = fma(kap, (double)(j - ra), q0);
+                        RowTaps<N> R;
+                        row_taps<N>(q, lc, s_tab, R);
+                        float* ar = s_a + (j - maj0) * W;
+                        float* kr = s_k + (j - maj0) * W;
+#pragma unroll
+                        for (int d = 0; d <= N; ++d) atomicAdd(ar + (R.J - d), sv * R.w[d]);
+#pragma unroll
+                        for (int sl = 0; sl <= N; ++sl) atomicAdd(kr + (R.K0 + sl), sv * R.e[sl]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // output = A + Delta^T K (forward difference of the knot accumulator)
+#pragma unroll
+        for (int e = 0; e < kPix; ++e) {
+            const int p = tid + e * kBlock;
+            const int pj = p / kTileI, pi = p % kTileI;  // pixel (row, column) in the tile
+            const int lmaj = vert ? pj : pi, lmin = vert ? pi : pj;
+            const float* ar = s_a + lmaj * W + kHalo + lmin;
+            const float* kr = s_k + lmaj * W + kHalo + lmin;
+            float v = ar[0];
+#pragma unroll
+            for (int l = 0; l <= N + 1; ++l) v = fmaf(delta_w<N>(l), kr[l], v);
+            o[e] += v;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < kPix; ++e) {
+        const int p = tid + e * kBlock;
+        const int pj = p / kTileI, pi = p % kTileI;
+        const int i = i0 + pi, j = j0 + pj;
+        if (i < A.nx && j < A.ny) A.out[(int64_t)j * A.nx + i] = o[e];
+    }
+}
+
+// ---------------------------------------------------------------- nnz
+struct NnzArgs {
+    int64_t m;
+    const PlanHeader* hdr;
+    const double* xc;
+    const double* kap;
+    int nx, ny, degree;
+    unsigned long long* out;
+};
+
+__global__ void __launch_bounds__(kBlock) k_nnz(NnzArgs A)
+{
+    __shared__ unsigned long long sh[kBlock];
+    int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long cnt = 0;
+    if (k < A.m && k < A.hdr->m_valid) {
+        const bool vert = k < A.hdr->m_vert;
+        const int nmaj = vert ? A.ny : A.nx, nmin = vert ? A.nx : A.ny;
+        const double kap = A.kap[k];
+        const double x0 = A.xc[k] - kap * (0.5 * (nmaj - 1));
+        const double W = 0.5 * (A.degree + 1) * (1.0 + fabs(kap));
+        int jlo, jhi;
+        row_range(x0, kap, W, nmaj, nmin, &jlo, &jhi);
+        for (int j = jlo; j <= jhi; ++j) {
+            const double X = x0 + kap * (double)j;
+            // integers i in (X - W, X + W) within [0, nmin - 1]
+            double lo = fmax(floor(X - W) + 1.0, 0.0);
+            double hi = fmin(ceil(X + W) - 1.0, (double)(nmin - 1));
+            if (hi >= lo) cnt += (unsigned long long)(hi - lo + 1.0);
+        }
+    }
+    sh[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int d = kBlock / 2; d > 0; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(A.out, sh[0]);
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_canon(const CanonArgs& a, hipStream_t s)
+{
+    if (a.m == 0) return hipSuccess;
+    dim3 grid((unsigned)((a.m + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_canon, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// Exclusive scan of n counts into out[0..n] (out[n] = total); tmp needs
+// room for the per-block partials of every level.
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s)
+{
+    const int64_t nblk = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nblk), dim3(kBlock), 0, s, in, out, tmp, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (nblk > 1) {
+        // scan the block totals (in place into tmp + nblk), then add
+        e = launch_scan(tmp, tmp + nblk, nblk, tmp + nblk + nblk + 1, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(kBlock), 0, s, out,
+                           (const uint32_t*)(tmp + nblk), n);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // total = scanned last partial + last block total
+        return hipMemcpyAsync(out + n, tmp + nblk + nblk, sizeof(uint32_t),
+                              hipMemcpyDeviceToDevice, s);
+    }
+    return hipMemcpyAsync(out + n, tmp, sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+}
+
+int64_t scan_tmp_words(int64_t n)
+{
+    int64_t w = 0;
+    while (true) {
+        int64_t nblk = (n + kScanTile - 1) / kScanTile;
+        w += nblk + nblk + 1;
+        if (nblk <= 1) break;
+        n = nblk;
+    }
+    return w + 16;
+}
+
+hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s)
+{
+    if (a.m == 0) return hipSuccess;
+    dim3 grid((unsigned)((a.m + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_scatter, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_header(PlanHeader* hdr, const uint32_t* off, int64_t vert_end, int64_t valid_end,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_header, dim3(1), dim3(1), 0, s, hdr, off, vert_end, valid_end);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t layouts_n(const xrt_plan* p, const float* coeffs, hipStream_t s)
+{
+    const int nx = p->g.nx, ny = p->g.ny;
+    dim3 gv((unsigned)((p->pitch_v + kBlock - 1) / kBlock), (unsigned)ny);
+    hipLaunchKernelGGL(k_layout_v<N>, gv, dim3(kBlock), 0, s, coeffs, nx, ny, p->pitch_v, p->cv,
+                       p->dv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 gh((unsigned)((p->pitch_h + kTr - 1) / kTr), (unsigned)((nx + kTr - 1) / kTr));
+    hipLaunchKernelGGL(k_layout_h<N>, gh, dim3(kBlock), 0, s, coeffs, nx, ny, p->pitch_h, p->ch,
+                       p->dh);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
+{
+    FwdArgs a;
+    a.m = p->m;
+    a.hdr = p->hdr;
+    a.xc = p->xc;
+    a.kap = p->kap;
+    a.idx = p->idx;
+    a.tab = p->tab;
+    a.cv = p->cv;
+    a.dv = p->dv;
+    a.ch = p->ch;
+    a.dh = p->dh;
+    a.pitch_v = p->pitch_v;
+    a.pitch_h = p->pitch_h;
+    a.nx = p->g.nx;
+    a.ny = p->g.ny;
+    a.h = p->g.h;
+    a.sino = sino;
+    a.nblk = (int)((p->m + kBlock - 1) / kBlock);
+    a.nblk_pad = (a.nblk + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_forward<N>, dim3((unsigned)a.nblk_pad), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, hipStream_t s)
+{
+    if (p->m == 0) return hipSuccess;
+    hipError_t e;
+    switch (p->degree) {
+    case 0: e = layouts_n<0>(p, coeffs, s); if (e == hipSuccess) e = forward_n<0>(p, sino, s); break;
+    case 1: e = layouts_n<1>(p, coeffs, s); if (e == hipSuccess) e = forward_n<1>(p, sino, s); break;
+    case 2: e = layouts_n<2>(p, coeffs, s); if (e == hipSuccess) e = forward_n<2>(p, sino, s); break;
+    default: e = layouts_n<3>(p, coeffs, s); if (e == hipSuccess) e = forward_n<3>(p, sino, s); break;
+    }
+    return e;
+}
+
+template <int N>
+static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
+{
+    AdjArgs a;
+    a.xc = p->xc;
+    a.kap = p->kap;
+    a.sw = p->sw;
+    a.off = p->off;
+    a.tab = p->tab;
+    a.nx = p->g.nx;
+    a.ny = p->g.ny;
+    a.nbk_v = p->nbk_v;
+    a.nbk_h = p->nbk_h;
+    a.boff_v = p->boff_v;
+    a.boff_h = p->boff_h;
+    a.tiles_i = (p->g.nx + kTileI - 1) / kTileI;
+    a.tiles_j = (p->g.ny + kTileJ - 1) / kTileJ;
+    a.ntiles = a.tiles_i * a.tiles_j;
+    a.ntiles_pad = (a.ntiles + 7) / 8 * 8;
+    a.out = out;
+    hipLaunchKernelGGL(k_adjoint<N>, dim3((unsigned)a.ntiles_pad), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s)
+{
+    if (p->m > 0) {
+        SortSinoArgs a;
+        a.m = p->m;
+        a.hdr = p->hdr;
+        a.kap = p->kap;
+        a.idx = p->idx;
+        a.sino = sino;
+        a.h = p->g.h;
+        a.sw = p->sw;
+        hipLaunchKernelGGL(k_sort_sino, dim3((unsigned)((p->m + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    switch (p->degree) {
+    case 0: return adjoint_n<0>(p, out, s);
+    case 1: return adjoint_n<1>(p, out, s);
+    case 2: return adjoint_n<2>(p, out, s);
+    default: return adjoint_n<3>(p, out, s);
+    }
+}
+
+hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s)
+{
+    if (p->m == 0) return hipSuccess;
+    NnzArgs a;
+    a.m = p->m;
+    a.hdr = p->hdr;
+    a.xc = p->xc;
+    a.kap = p->kap;
+    a.nx = p->g.nx;
+    a.ny = p->g.ny;
+    a.degree = p->degree;
+    a.out = out;
+    hipLaunchKernelGGL(k_nnz, dim3((unsigned)((p->m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace xrt

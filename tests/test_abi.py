@@ -1,0 +1,109 @@
+"""Host-side tests of the C ABI: the library loads without a GPU, exports every
+symbol include/xrt.h declares, and rejects bad arguments synchronously,
+before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2503_20907_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "xrt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(xrt_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = header_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTS) == names
+
+
+def test_version_and_status_strings():
+    assert re.match(r"\d+\.\d+\.\d+", L.xrt_version())
+    for st in (L.XRT_OK, L.XRT_EINVAL, L.XRT_EDEGREE, L.XRT_ESIZE, L.XRT_ENOMEM, L.XRT_EHIP,
+               L.XRT_EPLAN):
+        assert L.xrt_status_string(st)
+    assert L.xrt_status_string(12345) == "unknown status"
+
+
+def grid(nx=16, ny=16, h=1.0):
+    return L.XrtGrid(nx, ny, h, 0.0, 0.0)
+
+
+def lines(n=4, kind=L.XRT_LINES_THETA_Y, ptr=0x1000):
+    return L.XrtLines(kind, n, ptr, ptr, ptr)
+
+
+FAKE = 0x1000  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("args,expected", [
+    (dict(coeffs=None), L.XRT_EINVAL),
+    (dict(degree=4), L.XRT_EDEGREE),
+    (dict(degree=-1), L.XRT_EDEGREE),
+    (dict(g=grid(0, 5)), L.XRT_EINVAL),
+    (dict(g=grid(5, -1)), L.XRT_EINVAL),
+    (dict(g=grid(5, 5, 0.0)), L.XRT_EINVAL),
+    (dict(g=grid(5, 5, float("nan"))), L.XRT_EINVAL),
+    (dict(g=grid(40000, 5)), L.XRT_ESIZE),
+    (dict(lines=lines(-1)), L.XRT_EINVAL),
+    (dict(lines=lines(2 ** 31)), L.XRT_ESIZE),
+    (dict(lines=lines(4, kind=7)), L.XRT_EINVAL),
+    (dict(lines=L.XrtLines(L.XRT_LINES_THETA_Y, 4, None, FAKE, None)), L.XRT_EINVAL),
+    (dict(lines=L.XrtLines(L.XRT_LINES_ENDPOINTS, 4, FAKE, FAKE, None)), L.XRT_EINVAL),
+    (dict(sino=None), L.XRT_EINVAL),
+])
+def test_forward_argument_errors(args, expected):
+    a = dict(coeffs=FAKE, g=grid(), degree=1, lines=lines(), sino=FAKE)
+    a.update(args)
+    st = L.xrt_forward(a["coeffs"], a["g"], a["degree"], a["lines"], a["sino"], None)
+    assert st == expected
+
+
+@pytest.mark.parametrize("args,expected", [
+    (dict(out=None), L.XRT_EINVAL),
+    (dict(sino=None), L.XRT_EINVAL),
+    (dict(degree=9), L.XRT_EDEGREE),
+    (dict(g=grid(3, 0)), L.XRT_EINVAL),
+    (dict(lines=lines(-5)), L.XRT_EINVAL),
+])
+def test_adjoint_argument_errors(args, expected):
+    a = dict(sino=FAKE, lines=lines(), degree=2, g=grid(), out=FAKE)
+    a.update(args)
+    assert L.xrt_adjoint(a["sino"], a["lines"], a["degree"], a["g"], a["out"], None) == expected
+
+
+def test_plan_argument_errors():
+    lib = L.load()
+    out = ctypes.c_void_p(123)
+    assert lib.xrt_plan_create(grid(), 5, ctypes.byref(lines()), None, ctypes.byref(out)) == \
+        L.XRT_EDEGREE
+    assert out.value is None
+    assert lib.xrt_plan_create(grid(0, 1), 1, ctypes.byref(lines()), None, ctypes.byref(out)) == \
+        L.XRT_EINVAL
+    assert lib.xrt_plan_create(grid(), 1, ctypes.byref(lines()), None, None) == L.XRT_EINVAL
+    # null / foreign plans
+    assert L.xrt_plan_forward(None, FAKE, FAKE, None) == L.XRT_EPLAN
+    assert L.xrt_plan_adjoint(None, FAKE, FAKE, None) == L.XRT_EPLAN
+    assert L.xrt_plan_info(None)[0] == L.XRT_EPLAN
+    assert L.xrt_plan_nnz(None, None)[0] == L.XRT_EPLAN
+    junk = (ctypes.c_uint64 * 64)()
+    assert L.xrt_plan_forward(ctypes.addressof(junk), FAKE, FAKE, None) == L.XRT_EPLAN
+    L.xrt_plan_destroy(None)
+    L.xrt_plan_destroy(ctypes.addressof(junk))  # not a plan: ignored
+
+
+def test_product_path_has_no_cpu_fallback():
+    torch = pytest.importorskip("torch")
+    from paper_2503_20907_amd import ops
+    with pytest.raises(ValueError):
+        ops.forward(torch.zeros(4, 4), ops.Lines(theta=[0.0], y=[0.0], device="cpu"), 1)
