@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--n-bins", type=int, default=3072)
     ap.add_argument("--grid", type=int, default=2048)
     ap.add_argument("--degree", type=int, default=3)
+    ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -90,6 +92,18 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_only:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel
+        # give the scale between the counters and bytes moved
+        nel = args.copy_only * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_only, "bytes_read": nel * 4,
+                          "bytes_written": nel * 4}), flush=True)
+        return
     N, n = args.grid, args.degree
     print(f"[bench] building workload {N}^2 degree {n}", file=sys.stderr, flush=True)
     spec, nfan = W.large_lines(args.n_src, args.n_bins, None, N, n)

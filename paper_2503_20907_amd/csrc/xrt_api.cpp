@@ -139,7 +139,7 @@ struct Allocs {
 void free_plan_memory(xrt_plan* p, hipStream_t s)
 {
     void* ptrs[] = {p->xc, p->kap, p->idx, p->off, p->hdr, p->tab,
-                    p->cv, p->dv, p->ch, p->dh, p->sw};
+                    p->cv, p->dv, p->ch, p->dh, p->sw, p->part};
     for (void* q : ptrs)
         if (q) (void)hipFreeAsync(q, s);
 }
@@ -208,6 +208,8 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     p->key_space = per_v + per_h + 1;
     p->pitch_v = round_up(g.nx + 2 * kPad, 16);
     p->pitch_h = round_up(g.ny + 2 * kPad, 16);
+    p->strips_v = (g.ny + kStrip - 1) / kStrip;
+    p->strips_h = (g.nx + kStrip - 1) / kStrip;
 
     const int64_t m = p->m;
     Allocs al{s};
@@ -222,6 +224,7 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     p->ch = al.get<float>((size_t)g.nx * p->pitch_h);
     p->dh = al.get<float>((size_t)g.nx * p->pitch_h);
     p->sw = al.get<float>(m);
+    p->part = al.get<float>((size_t)m * (size_t)(p->strips_v > p->strips_h ? p->strips_v : p->strips_h));
     // temporaries
     uint32_t* key = al.get<uint32_t>(m);
     double* xc_in = al.get<double>(m);

@@ -23,6 +23,9 @@ constexpr int kTileJ = 64;
 // Halo (cells) of the LDS accumulators of the adjoint on each minor side.
 constexpr int kHalo = 10;
 constexpr int kBlock = 256;
+// Rows per strip of the forward's strip-major schedule (one strip of the
+// coefficient layouts, about 2 MB at 2048 columns, stays in an XCD's L2).
+constexpr int kStrip = 128;
 
 // Number of knot-transition slots per row for degree n.
 __host__ __device__ constexpr int n_slots(int n) { return n + 1; }
@@ -109,4 +112,6 @@ struct xrt_plan {
     int pitch_v, pitch_h;
     float *cv, *dv, *ch, *dh;  // coefficient / difference layouts
     float* sw;                 // sinogram in sorted order, scaled
+    float* part;               // forward partial sums, [max strips][m]
+    int strips_v, strips_h;    // strips of kStrip rows, per orientation
 };

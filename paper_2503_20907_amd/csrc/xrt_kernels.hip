@@ -299,115 +299,157 @@ __global__ void __launch_bounds__(kBlock) k_layout_h(const float* __restrict__ c
 }
 
 // ---------------------------------------------------------------- row math
-// Constants of one line: r = |kappa|, 1/r, r^n, the beta'' weight rho.
+// Constants of one line: 64/r (table units), r^n, the beta'' weight rho, and
+// the number of knot slots S = ceil((n+1) r) (at most n+1) that can be
+// non-zero in a row: only knots within (n+1) r / 2 of the crossing matter.
 struct LineConst {
-    float inv_r, rn, rho;
+    float inv64, rn, rho;
+    int slots;
 };
 
 template <int N>
 __device__ inline LineConst line_const(double kap)
 {
     LineConst k;
-    float r = (float)fabs(kap);
-    k.inv_r = 1.0f / fmaxf(r, 1e-30f);
+    const float r = (float)fabs(kap);
+    k.inv64 = (float)kTabPerUnit / fmaxf(r, 1e-30f);
     float rn = 1.f;
 #pragma unroll
     for (int e = 0; e < N; ++e) rn *= r;
     k.rn = rn;
     // (r^2/2) * mu_2 with mu_2 = (n+1)/12; the term exists for n >= 2
     k.rho = N >= 2 ? r * r * (float)(N + 1) / 24.0f : 0.f;
+    const int sl = (int)ceilf((float)(N + 1) * r);
+    k.slots = sl < 1 ? 1 : (sl > N + 1 ? N + 1 : sl);
     return k;
 }
 
-// Knot-transition table lookup: g(|z|) with the parity of E.
+// Slot count shared by the active lanes of a wave (the largest one).
 template <int N>
-__device__ inline float etab(const float4* __restrict__ tab, float z)
+__device__ inline int wave_slots(int mine)
 {
-    constexpr float last = (float)(kTabPerUnit * (N + 1)) * 0.5f;  // index of the zero interval
-    float a = fabsf(z) * (float)kTabPerUnit;
-    a = fminf(a, last);
-    int i = (int)a;
-    float tau = a - (float)i;
-    float4 cf = tab[i];
+    int S = 1;
+#pragma unroll
+    for (int v = 2; v <= N + 1; ++v)
+        if (__ballot(mine >= v) != 0) S = v;
+    return S;
+}
+
+// Knot-transition table at z64 = 64 z: g(|z|) with the parity of E
+// (E is even for odd n; for even n it changes sign at 0).
+template <int N>
+__device__ inline float etab64(const float4* __restrict__ tab, float z64)
+{
+    constexpr int last = kTabPerUnit * (N + 1) / 2;  // index of the zero interval
+    const float a = fminf(fabsf(z64), (float)last);
+    const int i = (int)a;
+    const float tau = __builtin_amdgcn_fractf(a);
+    const float4 cf = tab[i];
     float g = fmaf(tau, fmaf(tau, fmaf(tau, cf.w, cf.z), cf.y), cf.x);
-    if constexpr (N % 2 == 0) g = z >= 0.f ? -g : g;
+    if constexpr (N % 2 == 0) g = z64 >= 0.f ? -g : g;
     return g;
 }
 
-// Everything one row needs: tap base J (taps J-d, d = 0..N) with weights w[d],
-// knot base K0 (slots K0 + s) with values e[s] (already times r^n).
-template <int N>
-struct RowTaps {
+// One row: taps J-d (d = 0..N) at fraction t; knots K0+s (s < S) with E
+// values g[s] (not yet multiplied by r^n).  q = X + (n+1)/2.
+template <int S>
+struct Row {
     int J, K0;
-    float w[N + 1];
-    float e[N + 1];
+    float t;
+    float g[S];
 };
 
-template <int N>
-__device__ inline void row_taps(double q, const LineConst& k, const float4* __restrict__ tab,
-                                RowTaps<N>& R)
+template <int N, int S>
+__device__ inline void row_core(double q, const LineConst& k, const float4* __restrict__ tab,
+                                Row<S>& R)
 {
-    // q = X + (n+1)/2; taps J - d carry beta^n(t + d - (n+1)/2) (+ rho beta'').
     const double Jd = floor(q);
     const float t = (float)(q - Jd);
     R.J = (int)Jd;
+    R.t = t;
+    // the S knots nearest to q: centred on round(q) for odd S, on q for even S
+    int o;
+    if constexpr (S % 2 == 1) o = (t >= 0.5f ? 1 : 0) - (S - 1) / 2;
+    else o = 1 - S / 2;
+    R.K0 = R.J + o;
+    // z_s = (q - K0 - s) / r, in table units
+    const float a0 = (t - (float)o) * k.inv64;
+    R.g[0] = etab64<N>(tab, a0);
+#pragma unroll
+    for (int sl = 1; sl < S; ++sl) R.g[sl] = etab64<N>(tab, fmaf(-(float)sl, k.inv64, a0));
+}
+
+// Weights of the taps J - d: beta^n(t + d - (n+1)/2), plus the
+// r^2 (mu_2/2) beta^n'' term (rho) for n >= 2.
+template <int N>
+__device__ inline void tap_weights(float t, float rho, float* w)
+{
     if constexpr (N == 0) {
-        R.w[0] = 1.f;
+        w[0] = 1.f;
     } else if constexpr (N == 1) {
-        R.w[0] = t;
-        R.w[1] = 1.f - t;
+        w[0] = t;
+        w[1] = 1.f - t;
     } else if constexpr (N == 2) {
         const float u = t - 0.5f, s = 1.f - t;
-        R.w[0] = 0.5f * t * t + k.rho;
-        R.w[1] = 0.75f - u * u - 2.f * k.rho;
-        R.w[2] = 0.5f * s * s + k.rho;
+        w[0] = fmaf(0.5f * t, t, rho);
+        w[1] = fmaf(-u, u, fmaf(-2.f, rho, 0.75f));
+        w[2] = fmaf(0.5f * s, s, rho);
     } else {
         const float t2 = t * t, t3 = t2 * t, s = 1.f - t;
-        const float s3 = s * s * s;
         const float r6 = 1.f / 6.f;
-        R.w[0] = t3 * r6 + k.rho * t;
-        R.w[3] = s3 * r6 + k.rho * s;
-        R.w[2] = fmaf(3.f * t3 - 6.f * t2 + 4.f, r6, k.rho * (3.f * t - 2.f));
-        R.w[1] = fmaf(-3.f * t3 + 3.f * t2 + 3.f * t + 1.f, r6, k.rho * (1.f - 3.f * t));
-    }
-    // knot slots: odd n use J, even n the nearest integer to q
-    if constexpr (N % 2 == 1) {
-        R.K0 = R.J - (N - 1) / 2;
-#pragma unroll
-        for (int sl = 0; sl <= N; ++sl) {
-            // z = (q - K)/r with K = K0 + sl:  q - K = t + (N-1)/2 - sl
-            float z = (t + (float)((N - 1) / 2 - sl)) * k.inv_r;
-            R.e[sl] = etab<N>(tab, z) * k.rn;
-        }
-    } else {
-        const double J2 = floor(q + 0.5);
-        const float t2 = (float)(q + 0.5 - J2);
-        R.K0 = (int)J2 - N / 2;
-#pragma unroll
-        for (int sl = 0; sl <= N; ++sl) {
-            // q - K = t2 - 0.5 + N/2 - sl
-            float z = (t2 + (float)(N / 2 - sl) - 0.5f) * k.inv_r;
-            R.e[sl] = etab<N>(tab, z) * k.rn;
-        }
+        w[0] = fmaf(t3, r6, rho * t);
+        w[3] = fmaf(s * s * s, r6, rho * s);
+        w[2] = fmaf(fmaf(3.f, t3, fmaf(-6.f, t2, 4.f)), r6, rho * fmaf(3.f, t, -2.f));
+        w[1] = fmaf(fmaf(-3.f, t3, fmaf(3.f, t2, fmaf(3.f, t, 1.f))), r6, rho * fmaf(-3.f, t, 1.f));
     }
 }
 
-// Loads of N+1 consecutive floats (pointer at the first).
+// sum_d w_d(t) c_{J-d} written in powers of t, times kTapScale<N> (c[0] is
+// c_{J-N}, c[N] is c_J).  For n = 3:
+//   6 S = (c0 + 4c1 + c2) + 3t (c2 - c0) + 3(t^2 + 2 rho)(c0 - 2c1 + c2)
+//         + t (t^2 + 6 rho)(c3 - c0 + 3(c1 - c2)).
 template <int N>
-__device__ inline void load_taps(const float* __restrict__ p, float* v)
+__device__ constexpr float tap_scale() { return N == 3 ? 6.f : 1.f; }
+
+template <int N>
+__device__ inline float tap_sum(float t, float rho, const float* c)
 {
     if constexpr (N == 0) {
-        v[0] = p[0];
+        return c[0];
     } else if constexpr (N == 1) {
+        return fmaf(t, c[1] - c[0], c[0]);
+    } else if constexpr (N == 2) {
+        // (c0 + c1)/2 + t (c1 - c0) + (t^2/2 + rho)(c0 - 2 c1 + c2)
+        const float d2 = fmaf(-2.f, c[1], c[0] + c[2]);
+        return fmaf(fmaf(0.5f * t, t, rho), d2, fmaf(t, c[1] - c[0], 0.5f * (c[0] + c[1])));
+    } else {
+        const float e0 = c[0] + c[2];
+        const float a0 = fmaf(4.f, c[1], e0);
+        const float a2 = fmaf(-2.f, c[1], e0);
+        const float a3 = fmaf(3.f, c[1] - c[2], c[3] - c[0]);
+        const float t3 = 3.f * t;
+        const float p2 = fmaf(t3, t, 6.f * rho);
+        const float p3 = t * fmaf(t, t, 6.f * rho);
+        return fmaf(a3, p3, fmaf(a2, p2, fmaf(c[2] - c[0], t3, a0)));
+    }
+}
+
+// Loads of C consecutive floats (pointer at the first).
+template <int C>
+__device__ inline void load_run(const float* __restrict__ p, float* v)
+{
+    if constexpr (C == 1) {
+        v[0] = p[0];
+    } else if constexpr (C == 2) {
         f2u a = *(const f2u*)p;
         v[0] = a.x;
         v[1] = a.y;
     } else {
-        f4u a = *(const f4u*)p;
+        f4u a = *(const f4u*)p;  // C = 3 reads one float of padding
         v[0] = a.x;
         v[1] = a.y;
         v[2] = a.z;
-        if constexpr (N == 3) v[3] = a.w;
+        if constexpr (C == 4) v[3] = a.w;
     }
 }
 
@@ -435,10 +477,45 @@ struct FwdArgs {
     int nx, ny;
     double h;
     float* sino;
+    float* part;  // [strips][m] partial sums
+    int strips_v, strips_h;
     int nblk, nblk_pad;
 };
 
-template <int N>
+// Sum over the rows [ja, jb] of one line (times tap_scale<N>).  C and D are
+// the layout bases (uniform); element (row j, minor i) sits at
+// j * pitch + kPad + i.
+template <int N, int S>
+__device__ inline float fwd_walk(double q, double kap, int ja, int jb, const LineConst& lc,
+                                 const float4* __restrict__ tab, const float* __restrict__ C,
+                                 const float* __restrict__ D, int pitch)
+{
+    const float rho = lc.rho;
+    const float ern = tap_scale<N>() * lc.rn;
+    uint32_t off = (uint32_t)ja * (uint32_t)pitch + kPad;
+    float part = 0.f;
+    for (int j = ja; j <= jb; ++j) {
+        Row<S> R;
+        row_core<N, S>(q, lc, tab, R);
+        float cv[N + 1], dv[S];
+        load_run<N + 1>(C + (off + (uint32_t)(R.J - N)), cv);  // c_{J-N} .. c_J
+        load_run<S>(D + (off + (uint32_t)R.K0), dv);
+        float es = R.g[0] * dv[0];
+#pragma unroll
+        for (int sl = 1; sl < S; ++sl) es = fmaf(R.g[sl], dv[sl], es);
+        part += fmaf(ern, es, tap_sum<N>(R.t, rho, cv));
+        q += kap;
+        off += (uint32_t)pitch;
+    }
+    return part;
+}
+
+// Forward, one launch per orientation.  The rows are cut into strips of
+// kStrip rows and the grid is strip-major (block b works on strip
+// b / nblk_pad), so the blocks in flight at any time read one strip of the
+// layout, which stays in L2.  Each (strip, line) writes its partial sum to
+// part[strip * m + k]; k_fwd_reduce adds the strips in order.
+template <int N, bool VERT>
 __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
 {
     __shared__ float4 s_tab[kTabMax];
@@ -446,46 +523,60 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
     __syncthreads();
 
-    const int lb = xcd_logical(blockIdx.x, A.nblk_pad);
-    if (lb >= A.nblk) return;
-    const int64_t k = (int64_t)lb * kBlock + threadIdx.x;
-    if (k >= A.m) return;
+    const int strip = blockIdx.x / A.nblk_pad;
+    const int bid = blockIdx.x % A.nblk_pad;
     const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
-    const int out = A.idx[k];
-    if (k >= m_valid) {
-        A.sino[out] = 0.f;
-        return;
-    }
-    const bool vert = k < m_vert;
+    // vertical lines are the sorted range [0, m_vert), horizontal ones
+    // [m_vert, m_valid).  The grid covers all m lines; the blocks of this
+    // launch's range are spread evenly over the XCDs and the rest return.
+    const int64_t first = VERT ? 0 : m_vert, end = VERT ? m_vert : m_valid;
+    const int nb = (int)((end - first + kBlock - 1) / kBlock);
+    const int nb_pad = (nb + 7) / 8 * 8;
+    if (bid >= nb_pad) return;
+    const int lb = xcd_logical(bid, nb_pad);
+    if (lb >= nb) return;
+    const int64_t k = first + (int64_t)lb * kBlock + threadIdx.x;
+    if (k >= end) return;
     const double xc = A.xc[k], kap = A.kap[k];
-    const int nmaj = vert ? A.ny : A.nx, nmin = vert ? A.nx : A.ny;
-    const int pitch = vert ? A.pitch_v : A.pitch_h;
-    const float* __restrict__ C = vert ? A.cv : A.ch;
-    const float* __restrict__ D = vert ? A.dv : A.dh;
+    const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
+    const int pitch = VERT ? A.pitch_v : A.pitch_h;
+    const float* __restrict__ C = VERT ? A.cv : A.ch;
+    const float* __restrict__ D = VERT ? A.dv : A.dh;
     const double H = 0.5 * (N + 1);
     const double x0 = xc - kap * (0.5 * (nmaj - 1));
     int jlo, jhi;
     row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+    const int ja = max(jlo, strip * kStrip), jb = min(jhi, strip * kStrip + kStrip - 1);
     const LineConst lc = line_const<N>(kap);
-    const double q0 = x0 + kap * (double)jlo + H;
-    double acc = 0.0;
-    for (int j = jlo; j <= jhi; ++j) {
-        const double q = fma(kap, (double)(j - jlo), q0);
-        RowTaps<N> R;
-        row_taps<N>(q, lc, s_tab, R);
-        const float* crow = C + (int64_t)j * pitch + kPad;
-        float cvv[N + 1], dvv[N + 1];
-        load_taps<N>(crow + (R.J - N), cvv);  // c_{J-N} .. c_J
-        load_taps<N>(D + (int64_t)j * pitch + kPad + R.K0, dvv);
-        float row = 0.f;
-#pragma unroll
-        for (int d = 0; d <= N; ++d) row = fmaf(R.w[d], cvv[N - d], row);
-#pragma unroll
-        for (int sl = 0; sl <= N; ++sl) row = fmaf(R.e[sl], dvv[sl], row);
-        acc += (double)row;
+    const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
+    float acc = 0.f;
+    if (ja <= jb) {
+        const double q0 = x0 + kap * (double)ja + H;
+        if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
     }
-    const double scale = A.h * sqrt(1.0 + kap * kap);
-    A.sino[out] = (float)(acc * scale);
+    A.part[(int64_t)strip * A.m + k] = acc;
+}
+
+// sino[idx[k]] = (sum over strips of part[s][k]) * h / max(|cos|,|sin|);
+// lines that miss the grid get 0.
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_fwd_reduce(FwdArgs A)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= A.m) return;
+    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
+    float v = 0.f;
+    if (k < m_valid) {
+        const int ns = k < m_vert ? A.strips_v : A.strips_h;
+        double acc = 0.0;
+        for (int st = 0; st < ns; ++st) acc += (double)A.part[(int64_t)st * A.m + k];
+        const double kap = A.kap[k];
+        v = (float)(acc * A.h * sqrt(1.0 + kap * kap) / (double)tap_scale<N>());
+    }
+    A.sino[A.idx[k]] = v;
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -547,48 +638,71 @@ __device__ constexpr int knot_shift() { return N == 0 ? 1 : N == 1 ? 2 : N == 2 
 
 // One line's contribution to the LDS accumulators of one tile: the rows of
 // the tile where the line's crossing lies within the tile's minor window.
+template <int N, int S>
+__device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float svs, float svk,
+                                const LineConst& lc, int W, const float4* __restrict__ s_tab,
+                                int* s_a, int* s_k)
+{
+    // start each lane at a different row so that the lanes of a wave rarely
+    // update the same LDS word in one instruction
+    int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
+    const float svkr = svk * lc.rn;
+    for (int c = 0; c < cnt; ++c) {
+        const double q = fma(kap, (double)jj, q0);
+        Row<S> R;
+        row_core<N, S>(q, lc, s_tab, R);
+        float w[N + 1];
+        tap_weights<N>(R.t, lc.rho, w);
+        int* ar = s_a + (row0 + jj) * W;
+        int* kr = s_k + (row0 + jj) * W;
+#pragma unroll
+        for (int d = 0; d <= N; ++d) atomicAdd(ar + (R.J - d), __float2int_rn(svs * w[d]));
+#pragma unroll
+        for (int sl = 0; sl < S; ++sl) atomicAdd(kr + (R.K0 + sl), __float2int_rn(svkr * R.g[sl]));
+        if (++jj == cnt) jj = 0;
+    }
+}
+
 template <int N>
-__device__ inline void adj_line(const AdjArgs& A, uint32_t k, float sv, int e, bool vert, int maj0,
-                                int min0, int TM, int TN, int nmaj, int W, double jc, double marg,
-                                const float4* __restrict__ s_tab, int* s_a, int* s_k)
+__device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float sv, int e,
+                                bool vert, int maj0, int min0, int TM, int TN, int nmaj, int W,
+                                double jc, double marg, const float4* __restrict__ s_tab, int* s_a,
+                                int* s_k)
 {
     const double H = 0.5 * (N + 1);
-    const double xc = A.xc[k], kap = A.kap[k];
-    const double x0 = xc - kap * jc;
-    const int nmin = vert ? A.nx : A.ny;
-    int jlo, jhi;
-    row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
-    int ra = max(jlo, maj0), rb = min(jhi, maj0 + TM - 1);
-    if (kap != 0.0) {
-        double a = (min0 - marg - x0) / kap, b = (min0 + TN - 1 + marg - x0) / kap;
-        double lo2 = fmin(a, b), hi2 = fmax(a, b);
-        ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
-        rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
-    } else if (!(x0 >= min0 - marg && x0 <= min0 + TN - 1 + marg)) {
-        rb = ra - 1;
+    int ra = 0, rb = -1;
+    double kap = 0.0, x0 = 0.0;
+    if (active) {
+        const double xc = A.xc[k];
+        kap = A.kap[k];
+        x0 = xc - kap * jc;
+        const int nmin = vert ? A.nx : A.ny;
+        int jlo, jhi;
+        row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+        ra = max(jlo, maj0);
+        rb = min(jhi, maj0 + TM - 1);
+        if (kap != 0.0) {
+            double a = (min0 - marg - x0) / kap, b = (min0 + TN - 1 + marg - x0) / kap;
+            double lo2 = fmin(a, b), hi2 = fmax(a, b);
+            ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
+            rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
+        } else if (!(x0 >= min0 - marg && x0 <= min0 + TN - 1 + marg)) {
+            rb = ra - 1;
+        }
     }
-    if (ra > rb) return;
+    const bool work = active && ra <= rb;
     const LineConst lc = line_const<N>(kap);
+    const int S = wave_slots<N>(work ? lc.slots : 1);
+    if (!work) return;
     const float svs = ldexpf(sv, e);
     const float svk = ldexpf(sv, e + knot_shift<N>());
     // local q: column index within the LDS row (halo included)
     const double q0 = x0 + kap * (double)ra + H - (double)min0 + (double)kHalo;
-    const int cnt = rb - ra + 1;
-    // start each lane at a different row so that the lanes of a wave rarely
-    // update the same LDS word in one instruction
-    int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
-    for (int c = 0; c < cnt; ++c) {
-        const double q = fma(kap, (double)jj, q0);
-        RowTaps<N> R;
-        row_taps<N>(q, lc, s_tab, R);
-        int* ar = s_a + (ra + jj - maj0) * W;
-        int* kr = s_k + (ra + jj - maj0) * W;
-#pragma unroll
-        for (int d = 0; d <= N; ++d) atomicAdd(ar + (R.J - d), __float2int_rn(svs * R.w[d]));
-#pragma unroll
-        for (int sl = 0; sl <= N; ++sl) atomicAdd(kr + (R.K0 + sl), __float2int_rn(svk * R.e[sl]));
-        if (++jj == cnt) jj = 0;
-    }
+    const int cnt = rb - ra + 1, row0 = ra - maj0;
+    if (S == 1) adj_walk<N, 1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    else if (S == 2) adj_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    else if (S == 3) adj_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    else adj_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
 }
 
 __device__ inline float block_max(float v, float* red)
@@ -695,8 +809,8 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(AdjArgs A)
             int em;
             (void)frexpf(mx, &em);
             const int e = 22 - em;  // |s| 2^e < 2^22
-            if (sv != 0.f)
-                adj_line<N>(A, k, sv, e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg, s_tab, s_a, s_k);
+            adj_line<N>(A, k, sv != 0.f, sv, e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg, s_tab,
+                        s_a, s_k);
             __syncthreads();
             // flush: output += (A + Delta^T K) 2^-e  (forward difference of K)
 #pragma unroll
@@ -863,9 +977,23 @@ static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
     a.ny = p->g.ny;
     a.h = p->g.h;
     a.sino = sino;
+    a.part = p->part;
+    a.strips_v = p->strips_v;
+    a.strips_h = p->strips_h;
+    // the split between vertical and horizontal lines is known on the device
+    // only: the grid of each launch covers all m lines (times the strips) and
+    // blocks past the launch's range return at once
     a.nblk = (int)((p->m + kBlock - 1) / kBlock);
     a.nblk_pad = (a.nblk + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_forward<N>, dim3((unsigned)a.nblk_pad), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_forward<N, true>), dim3((unsigned)(a.nblk_pad * p->strips_v)), dim3(kBlock),
+                       0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_forward<N, false>), dim3((unsigned)(a.nblk_pad * p->strips_h)),
+                       dim3(kBlock), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fwd_reduce<N>, dim3((unsigned)a.nblk), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
