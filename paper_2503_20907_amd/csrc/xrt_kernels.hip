@@ -395,12 +395,16 @@ __device__ inline void tap_weights(float t, float rho, float* w)
         w[1] = fmaf(-u, u, fmaf(-2.f, rho, 0.75f));
         w[2] = fmaf(0.5f * s, s, rho);
     } else {
-        const float t2 = t * t, t3 = t2 * t, s = 1.f - t;
-        const float r6 = 1.f / 6.f;
-        w[0] = fmaf(t3, r6, rho * t);
-        w[3] = fmaf(s * s * s, r6, rho * s);
-        w[2] = fmaf(fmaf(3.f, t3, fmaf(-6.f, t2, 4.f)), r6, rho * fmaf(3.f, t, -2.f));
-        w[1] = fmaf(fmaf(-3.f, t3, fmaf(3.f, t2, fmaf(3.f, t, 1.f))), r6, rho * fmaf(-3.f, t, 1.f));
+        // with h2 = (t^2 + 2 rho)/2 and h3 = t (t^2 + 6 rho)/6:
+        //   w0 = h3, w3 = 1/6 - t/2 + h2 - h3, w1 = 1/6 + t/2 + h2 - 3 h3,
+        //   w2 = 2/3 - 2 h2 + 3 h3
+        const float h2 = fmaf(0.5f * t, t, rho);
+        const float h3 = (t * (1.f / 6.f)) * fmaf(t, t, 6.f * rho);
+        const float u = (1.f / 6.f) + h2 - h3;
+        w[0] = h3;
+        w[3] = fmaf(-0.5f, t, u);
+        w[1] = fmaf(0.5f, t, fmaf(-2.f, h3, u));
+        w[2] = fmaf(3.f, h3, fmaf(-2.f, h2, 2.f / 3.f));
     }
 }
 
@@ -492,20 +496,25 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
 {
     const float rho = lc.rho;
     const float ern = tap_scale<N>() * lc.rn;
-    uint32_t off = (uint32_t)ja * (uint32_t)pitch + kPad;
+    // byte offsets (the layouts are below 4 GiB), so that the loads take the
+    // uniform base plus a 32-bit offset
+    const char* __restrict__ Cb = (const char*)C;
+    const char* __restrict__ Db = (const char*)D;
+    uint32_t off = ((uint32_t)ja * (uint32_t)pitch + kPad) * 4u;
+    const uint32_t step = (uint32_t)pitch * 4u;
     float part = 0.f;
     for (int j = ja; j <= jb; ++j) {
         Row<S> R;
         row_core<N, S>(q, lc, tab, R);
         float cv[N + 1], dv[S];
-        load_run<N + 1>(C + (off + (uint32_t)(R.J - N)), cv);  // c_{J-N} .. c_J
-        load_run<S>(D + (off + (uint32_t)R.K0), dv);
+        load_run<N + 1>((const float*)(Cb + (off + (uint32_t)(R.J - N) * 4u)), cv);
+        load_run<S>((const float*)(Db + (off + (uint32_t)R.K0 * 4u)), dv);
         float es = R.g[0] * dv[0];
 #pragma unroll
         for (int sl = 1; sl < S; ++sl) es = fmaf(R.g[sl], dv[sl], es);
         part += fmaf(ern, es, tap_sum<N>(R.t, rho, cv));
         q += kap;
-        off += (uint32_t)pitch;
+        off += step;
     }
     return part;
 }
@@ -616,28 +625,38 @@ struct AdjArgs {
     float* out;
 };
 
-constexpr int kAccW = (kTileI > kTileJ ? kTileI : kTileJ) + 2 * kHalo;
+// accumulator rows are padded to an odd pitch so that the rows the lanes of a
+// wave update fall into different LDS banks
+constexpr int kAccW = (kTileI > kTileJ ? kTileI : kTileJ) + 2 * kHalo + 1;
 constexpr int kAccRows = kTileI > kTileJ ? kTileI : kTileJ;
 constexpr int kPix = kTileI * kTileJ / kBlock;
 
 // The LDS accumulators are int32 fixed point: float atomic adds to LDS are an
 // order of magnitude slower than integer ones on gfx950.  Lines are taken in
-// chunks of kBlock (one per thread); a chunk scales the tap contributions by
-// 2^e with e = 22 - exponent(max |s| over the chunk), so each of them
-// (|s w| <= |s|, since |w| <= 1) is below 2^22 in magnitude and the at most
-// kBlock contributions a chunk makes to one accumulator word (one per line)
+// chunks of 2 kBlock (two per thread); a chunk scales the tap contributions by
+// 2^e with e = 21 - exponent(max |s| over the chunk), so each of them
+// (|s w| <= |s|, since |w| <= 1) is below 2^21 in magnitude and the at most
+// 2 kBlock contributions a chunk makes to one accumulator word (one per line)
 // stay below 2^30.  The knot contributions r^n E s are bounded by G(0) |s|
 // (G(0) = 1/2, 1/6, 1/16, 0.0246 for n = 0..3) and get 2^kKnotShift more
 // resolution under the same bound.  After each chunk the integers are
 // converted back (scaled exactly by powers of two) into per-thread FP32
-// outputs and cleared.  The rounding to integers is at most 2^-23 max|s| per
-// contribution, the size of an FP32 rounding, and the integer sums do not
-// depend on the order of the atomics.
+// outputs and cleared.  The rounding to integers is at most 2^-22 max|s| per
+// contribution, about an FP32 rounding, and the integer sums do not depend on
+// the order of the atomics.
 template <int N>
 __device__ constexpr int knot_shift() { return N == 0 ? 1 : N == 1 ? 2 : N == 2 ? 4 : 5; }
 
-// One line's contribution to the LDS accumulators of one tile: the rows of
-// the tile where the line's crossing lies within the tile's minor window.
+// Round-to-nearest integer of a float below 2^22 in magnitude: adding
+// 1.5 * 2^23 leaves exactly the rounded value in the mantissa.
+constexpr float kRoundMagic = 12582912.0f;
+constexpr int kRoundMagicBits = 0x4B400000;
+
+__device__ inline int fixed_round(float a, float b)
+{
+    return __float_as_int(fmaf(a, b, kRoundMagic)) - kRoundMagicBits;
+}
+
 template <int N, int S>
 __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float svs, float svk,
                                 const LineConst& lc, int W, const float4* __restrict__ s_tab,
@@ -653,12 +672,13 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
         row_core<N, S>(q, lc, s_tab, R);
         float w[N + 1];
         tap_weights<N>(R.t, lc.rho, w);
-        int* ar = s_a + (row0 + jj) * W;
-        int* kr = s_k + (row0 + jj) * W;
+        const uint32_t rb = __umul24((uint32_t)(row0 + jj), (uint32_t)W);
+        int* ar = s_a + (rb + (uint32_t)(R.J - N));  // taps J-N .. J, ascending
+        int* kr = s_k + (rb + (uint32_t)R.K0);
 #pragma unroll
-        for (int d = 0; d <= N; ++d) atomicAdd(ar + (R.J - d), __float2int_rn(svs * w[d]));
+        for (int d = 0; d <= N; ++d) atomicAdd(ar + d, fixed_round(svs, w[N - d]));
 #pragma unroll
-        for (int sl = 0; sl < S; ++sl) atomicAdd(kr + (R.K0 + sl), __float2int_rn(svkr * R.g[sl]));
+        for (int sl = 0; sl < S; ++sl) atomicAdd(kr + sl, fixed_round(svkr, R.g[sl]));
         if (++jj == cnt) jj = 0;
     }
 }
@@ -747,7 +767,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(AdjArgs A)
         const int maj0 = vert ? j0 : i0, min0 = vert ? i0 : j0;
         const int TM = vert ? kTileJ : kTileI, TN = vert ? kTileI : kTileJ;
         const int nmaj = vert ? A.ny : A.nx;
-        const int W = TN + 2 * kHalo;
+        const int W = TN + 2 * kHalo + 1;  // odd pitch
         const int nbk = vert ? A.nbk_v : A.nbk_h;
         const int boff = vert ? A.boff_v : A.boff_h;
         const uint32_t cls_base = vert ? 0u : (uint32_t)kSlopeBins * (uint32_t)A.nbk_v;
@@ -789,28 +809,33 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(AdjArgs A)
         __syncthreads();
         const uint32_t total = s_pre[kSlopeBins];
 
-        for (uint32_t base = 0; base < total; base += kBlock) {
-            const uint32_t item = base + tid;
-            uint32_t k = 0;
-            float sv = 0.f;
-            if (item < total) {
-                // bin b with s_pre[b] <= item < s_pre[b+1]
-                int lo = 0, hi = kSlopeBins;
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (s_pre[mid] <= item) lo = mid;
-                    else hi = mid;
+        for (uint32_t base = 0; base < total; base += 2 * kBlock) {
+            uint32_t kk[2] = {0, 0};
+            float svv[2] = {0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const uint32_t item = base + (uint32_t)(u * kBlock + tid);
+                if (item < total) {
+                    // bin b with s_pre[b] <= item < s_pre[b+1]
+                    int lo = 0, hi = kSlopeBins;
+                    while (hi - lo > 1) {
+                        int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= item) lo = mid;
+                        else hi = mid;
+                    }
+                    kk[u] = s_start[lo] + (item - s_pre[lo]);
+                    svv[u] = A.sw[kk[u]];
                 }
-                k = s_start[lo] + (item - s_pre[lo]);
-                sv = A.sw[k];
             }
-            const float mx = block_max(fabsf(sv), s_red);
+            const float mx = block_max(fmaxf(fabsf(svv[0]), fabsf(svv[1])), s_red);
             if (!(mx > 0.f)) continue;  // uniform: nothing to add in this chunk
             int em;
             (void)frexpf(mx, &em);
-            const int e = 22 - em;  // |s| 2^e < 2^22
-            adj_line<N>(A, k, sv != 0.f, sv, e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg, s_tab,
-                        s_a, s_k);
+            const int e = 21 - em;  // |s| 2^e < 2^21
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                adj_line<N>(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
+                            jc, marg, s_tab, s_a, s_k);
             __syncthreads();
             // flush: output += (A + Delta^T K) 2^-e  (forward difference of K)
 #pragma unroll
