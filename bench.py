@@ -25,6 +25,27 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 G
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or None if
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2503_20907_amd", "csrc", "xrt_kernels.hip")
+    summ = os.path.join(ROOT, "profiles", "hbm_traffic_2048_cubic_fan_random.md")
+    if not (os.path.exists(src) and os.path.exists(summ)):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    total = 0
+    found = False
+    for line in open(summ):
+        m = re.search(r"traffic kernel=(\S+) sha=(\w+) read_bytes=(\d+) write_bytes=(\d+)", line)
+        if m and m.group(1).startswith(kernel) and m.group(2) == sha:
+            total += int(m.group(3)) + int(m.group(4))
+            found = True
+    return total if found else None
+
+
 def flops_per_nonzero(n: int) -> int:
     # one degree-(2n+1) polynomial evaluation (2n+1 FMAs) + one FMA, 2 flops each
     return 4 * n + 4
@@ -154,7 +175,8 @@ def main():
     achieved = nnz * F / t_dom / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": None, "kernel": dominant,
+                "traffic": measured_traffic("k_adjoint<" if dominant == "adjoint" else "k_forward<"),
+                "kernel": dominant,
                 "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                 "work": f"nnz(H) = {nnz} basis evaluations x {F} flops per launch"}
 
