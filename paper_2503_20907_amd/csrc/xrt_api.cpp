@@ -224,7 +224,7 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     p->ch = al.get<float>((size_t)g.nx * p->pitch_h);
     p->dh = al.get<float>((size_t)g.nx * p->pitch_h);
     p->sw = al.get<float>(m);
-    p->part = al.get<float>((size_t)m * (size_t)(p->strips_v > p->strips_h ? p->strips_v : p->strips_h));
+    p->part = al.get<double>(m);
     // temporaries
     uint32_t* key = al.get<uint32_t>(m);
     double* xc_in = al.get<double>(m);

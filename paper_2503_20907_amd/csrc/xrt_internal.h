@@ -112,6 +112,6 @@ struct xrt_plan {
     int pitch_v, pitch_h;
     float *cv, *dv, *ch, *dh;  // coefficient / difference layouts
     float* sw;                 // sinogram in sorted order, scaled
-    float* part;               // forward partial sums, [max strips][m]
+    double* part;              // forward sums over strips, [m]
     int strips_v, strips_h;    // strips of kStrip rows, per orientation
 };

@@ -481,8 +481,9 @@ struct FwdArgs {
     int nx, ny;
     double h;
     float* sino;
-    float* part;  // [strips][m] partial sums
+    double* part;  // [m] sums over the strips done so far
     int strips_v, strips_h;
+    int strip;     // strip of this launch
     int nblk, nblk_pad;
 };
 
@@ -519,11 +520,11 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     return part;
 }
 
-// Forward, one launch per orientation.  The rows are cut into strips of
-// kStrip rows and the grid is strip-major (block b works on strip
-// b / nblk_pad), so the blocks in flight at any time read one strip of the
-// layout, which stays in L2.  Each (strip, line) writes its partial sum to
-// part[strip * m + k]; k_fwd_reduce adds the strips in order.
+// Forward, one launch per (orientation, strip of kStrip rows): the blocks in
+// flight at any time read one strip of the layout, which stays in L2.  The
+// launches of one orientation run in strip order and each adds its partial
+// sums into part[k] (the first one writes), so the sum is deterministic;
+// k_fwd_reduce scales and scatters.
 template <int N, bool VERT>
 __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
 {
@@ -532,8 +533,8 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
     __syncthreads();
 
-    const int strip = blockIdx.x / A.nblk_pad;
-    const int bid = blockIdx.x % A.nblk_pad;
+    const int strip = A.strip;
+    const int bid = blockIdx.x;
     const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
     // vertical lines are the sorted range [0, m_vert), horizontal ones
     // [m_vert, m_valid).  The grid covers all m lines; the blocks of this
@@ -566,7 +567,8 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
         else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
         else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
     }
-    A.part[(int64_t)strip * A.m + k] = acc;
+    if (strip == 0) A.part[k] = (double)acc;
+    else if (ja <= jb) A.part[k] += (double)acc;
 }
 
 // sino[idx[k]] = (sum over strips of part[s][k]) * h / max(|cos|,|sin|);
@@ -576,12 +578,10 @@ __global__ void __launch_bounds__(kBlock) k_fwd_reduce(FwdArgs A)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= A.m) return;
-    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
+    const int64_t m_valid = A.hdr->m_valid;
     float v = 0.f;
     if (k < m_valid) {
-        const int ns = k < m_vert ? A.strips_v : A.strips_h;
-        double acc = 0.0;
-        for (int st = 0; st < ns; ++st) acc += (double)A.part[(int64_t)st * A.m + k];
+        const double acc = A.part[k];
         const double kap = A.kap[k];
         v = (float)(acc * A.h * sqrt(1.0 + kap * kap) / (double)tap_scale<N>());
     }
@@ -1006,18 +1006,25 @@ static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
     a.strips_v = p->strips_v;
     a.strips_h = p->strips_h;
     // the split between vertical and horizontal lines is known on the device
-    // only: the grid of each launch covers all m lines (times the strips) and
-    // blocks past the launch's range return at once
+    // only: the grid of each launch covers all m lines and blocks past the
+    // launch's range return at once
     a.nblk = (int)((p->m + kBlock - 1) / kBlock);
     a.nblk_pad = (a.nblk + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_forward<N, true>), dim3((unsigned)(a.nblk_pad * p->strips_v)), dim3(kBlock),
-                       0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_forward<N, false>), dim3((unsigned)(a.nblk_pad * p->strips_h)),
-                       dim3(kBlock), 0, s, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int ns = p->strips_v > p->strips_h ? p->strips_v : p->strips_h;
+    for (int st = 0; st < ns; ++st) {
+        a.strip = st;
+        if (st < p->strips_v) {
+            hipLaunchKernelGGL((k_forward<N, true>), dim3((unsigned)a.nblk_pad), dim3(kBlock), 0, s, a);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (st < p->strips_h) {
+            hipLaunchKernelGGL((k_forward<N, false>), dim3((unsigned)a.nblk_pad), dim3(kBlock), 0, s,
+                               a);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
     hipLaunchKernelGGL(k_fwd_reduce<N>, dim3((unsigned)a.nblk), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }

@@ -139,3 +139,39 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Project(torch.autograd.Function):
+    """s = H c as a differentiable operation: the backward pass is the exact
+    adjoint, grad_c = H^T grad_s (the matched back-projection).  The plan
+    (geometry, degree) is not differentiable."""
+
+    @staticmethod
+    def forward(ctx, coeffs: torch.Tensor, plan: "Plan") -> torch.Tensor:
+        ctx.plan = plan
+        return plan.forward(coeffs.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_sino: torch.Tensor):
+        return ctx.plan.adjoint(grad_sino.contiguous()), None
+
+
+class BackProject(torch.autograd.Function):
+    """c = H^T s as a differentiable operation (its backward is H)."""
+
+    @staticmethod
+    def forward(ctx, sino: torch.Tensor, plan: "Plan") -> torch.Tensor:
+        ctx.plan = plan
+        return plan.adjoint(sino.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_coeffs: torch.Tensor):
+        return ctx.plan.forward(grad_coeffs.contiguous()), None
+
+
+def project(coeffs: torch.Tensor, plan: "Plan") -> torch.Tensor:
+    return Project.apply(coeffs, plan)
+
+
+def backproject(sino: torch.Tensor, plan: "Plan") -> torch.Tensor:
+    return BackProject.apply(sino, plan)
