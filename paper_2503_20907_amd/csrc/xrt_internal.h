@@ -17,11 +17,21 @@ constexpr int kSlopeBins = 512;
 constexpr int kTabPerUnit = 64;
 // Largest table: degree 3, half-support 2 -> 128 intervals + 1 zero interval.
 constexpr int kTabMax = kTabPerUnit * 2 + 1;
-// Adjoint tile (pixels): kTileI columns (x1) by kTileJ rows (x2).
-constexpr int kTileI = 64;
-constexpr int kTileJ = 64;
-// Halo (cells) of the LDS accumulators of the adjoint on each minor side.
-constexpr int kHalo = 10;
+// Adjoint tile (pixels): kTileI columns (x1) by kTileJ rows (x2).  64 x 32
+// (32 KB of LDS, <= 128 VGPRs, 4 waves per SIMD) measured fastest among
+// 32..128-wide tiles on the 2048^2 cubic workload.
+#ifndef XRT_TILE_I
+#define XRT_TILE_I 64
+#endif
+#ifndef XRT_TILE_J
+#define XRT_TILE_J 32
+#endif
+constexpr int kTileI = XRT_TILE_I;
+constexpr int kTileJ = XRT_TILE_J;
+// Halo (cells) of the LDS accumulators of the adjoint on each minor side:
+// with crossings kept within n+1 cells of the tile, taps and knot slots stay
+// within 7 cells (degree 3) of it.
+constexpr int kHalo = 8;
 constexpr int kBlock = 256;
 // Rows per strip of the forward's strip-major schedule (one strip of the
 // coefficient layouts, about 2 MB at 2048 columns, stays in an XCD's L2).

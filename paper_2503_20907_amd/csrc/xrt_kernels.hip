@@ -627,8 +627,11 @@ struct AdjArgs {
 
 // accumulator rows are padded to an odd pitch so that the rows the lanes of a
 // wave update fall into different LDS banks
-constexpr int kAccW = (kTileI > kTileJ ? kTileI : kTileJ) + 2 * kHalo + 1;
-constexpr int kAccRows = kTileI > kTileJ ? kTileI : kTileJ;
+// words per accumulator: the vertical pass holds kTileJ rows of the tile's
+// columns, the horizontal pass kTileI rows of its rows (each with halos)
+constexpr int kAccWords = (kTileJ * (kTileI + 2 * kHalo + 1) > kTileI * (kTileJ + 2 * kHalo + 1))
+                              ? kTileJ * (kTileI + 2 * kHalo + 1)
+                              : kTileI * (kTileJ + 2 * kHalo + 1);
 constexpr int kPix = kTileI * kTileJ / kBlock;
 
 // The LDS accumulators are int32 fixed point: float atomic adds to LDS are an
@@ -736,11 +739,16 @@ __device__ inline float block_max(float v, float* red)
     return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
+// 4 waves per SIMD: the register budget that matches the LDS of a 64 x 32 tile
+#ifndef XRT_ADJ_WAVES
+#define XRT_ADJ_WAVES 4
+#endif
+#define XRT_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(XRT_ADJ_WAVES, XRT_ADJ_WAVES)))
 template <int N>
-__global__ void __launch_bounds__(kBlock) k_adjoint(AdjArgs A)
+__global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
 {
-    __shared__ int s_a[kAccRows * kAccW];
-    __shared__ int s_k[kAccRows * kAccW];
+    __shared__ int s_a[kAccWords];
+    __shared__ int s_k[kAccWords];
     __shared__ float4 s_tab[kTabMax];
     __shared__ uint32_t s_start[kSlopeBins];
     __shared__ uint32_t s_pre[kSlopeBins + 1];
@@ -755,7 +763,11 @@ __global__ void __launch_bounds__(kBlock) k_adjoint(AdjArgs A)
     if (tile >= A.ntiles) return;  // uniform per block
     const int ti = tile % A.tiles_i, tj = tile / A.tiles_i;
     const int i0 = ti * kTileI, j0 = tj * kTileJ;
-    const double marg = (double)N + 2.5;
+    // a row whose crossing X lies outside (min0 - (n+1), min0 + TN + n) adds
+    // nothing to the tile's outputs: its taps J-d (J = floor(X + (n+1)/2))
+    // miss [min0, min0 + TN) and its knots (within (n+1)/2 of X + (n+1)/2)
+    // miss [min0, min0 + TN + n]
+    const double marg = (double)N + 1.0;
 
     float o[kPix];
 #pragma unroll
