@@ -1,0 +1,191 @@
+"""Pins of the reconstruction / learned-preconditioner oracle (oracle/recon.py)
+against facts that do not come from the oracle itself: library routines for
+textbook special cases, closed-form eigenpairs, transposition identities,
+finite differences and dense linear algebra."""
+import math
+
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+import oracle
+import oracle.recon as R
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ----------------------------------------------------------------- convolution
+def test_conv3x3_matches_scipy_correlate():
+    rng = _rng(1)
+    B, H, W, ci, co = 2, 7, 9, 3, 4
+    x = rng.normal(size=(B, H, W, ci))
+    w = rng.normal(size=(9, co, ci))
+    y = R.conv3x3(x, w)
+    for b in range(B):
+        for o in range(co):
+            ref = np.zeros((H, W))
+            for i in range(ci):
+                k = w[:, o, i].reshape(3, 3)      # k[ky][kx] multiplies x[h+ky-1, w+kx-1]
+                ref += correlate2d(x[b, :, :, i], k, mode="same", boundary="fill")
+            assert np.allclose(y[b, :, :, o], ref, atol=1e-12)
+
+
+def test_conv3x3_grad_input_is_the_transpose():
+    rng = _rng(2)
+    x = rng.normal(size=(2, 6, 5, 3))
+    g = rng.normal(size=(2, 6, 5, 4))
+    w = rng.normal(size=(9, 4, 3))
+    lhs = np.sum(R.conv3x3(x, w) * g)
+    rhs = np.sum(x * R.conv3x3_grad_input(g, w))
+    assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(lhs))
+
+
+def test_conv3x3_grad_weight_by_linearity():
+    # sum(g * conv(x, w)) is linear in w, so it equals <grad_weight(x, g), w>
+    rng = _rng(3)
+    x = rng.normal(size=(2, 5, 6, 3))
+    g = rng.normal(size=(2, 5, 6, 4))
+    for _ in range(3):
+        w = rng.normal(size=(9, 4, 3))
+        lhs = np.sum(g * R.conv3x3(x, w))
+        rhs = np.sum(R.conv3x3_grad_weight(x, g) * w)
+        assert abs(lhs - rhs) < 1e-10 * max(1.0, abs(lhs))
+
+
+def test_conv3x3_single_tap_is_a_shift():
+    # a weight with one nonzero tap (ky, kx) shifts the image by (ky-1, kx-1)
+    rng = _rng(4)
+    x = rng.normal(size=(1, 5, 5, 1))
+    for ky in range(3):
+        for kx in range(3):
+            w = np.zeros((9, 1, 1))
+            w[3 * ky + kx, 0, 0] = 1.0
+            y = R.conv3x3(x, w)[0, :, :, 0]
+            for h in range(5):
+                for c in range(5):
+                    hh, cc = h + ky - 1, c + kx - 1
+                    want = x[0, hh, cc, 0] if 0 <= hh < 5 and 0 <= cc < 5 else 0.0
+                    assert y[h, c] == want
+
+
+def test_pool_and_upsample_transposes():
+    rng = _rng(5)
+    a = rng.normal(size=(2, 8, 6, 3))
+    c = rng.normal(size=(2, 4, 3, 3))
+    assert abs(np.sum(R.avgpool2(a) * c) - np.sum(a * R.avgpool2_T(c))) < 1e-12
+    assert abs(np.sum(R.upsample2(c) * a) - np.sum(c * R.upsample2_T(a))) < 1e-12
+    assert np.allclose(R.avgpool2(R.upsample2(c)), c)
+    assert np.allclose(R.avgpool2(np.full((1, 4, 4, 1), 2.5)), 2.5)
+
+
+# ----------------------------------------------------------------------- U-Net
+@pytest.mark.parametrize("levels,base", [(2, 2), (3, 2)])
+def test_unet_gradient_matches_central_differences(levels, base):
+    rng = _rng(6 + levels)
+    shapes = [s for _, s in R.unet_layout(levels, base)]
+    n = sum(int(np.prod(s)) for s in shapes)
+    flat = rng.normal(size=n) * 0.5
+    r = rng.normal(size=(2, 8, 8))
+    e = rng.normal(size=(2, 8, 8))
+    loss, g = R.precond_loss(flat, r, e, levels, base)
+    h = 1e-6
+    idx = rng.choice(n, 40, replace=False)
+    for k in idx:
+        fp, fm = flat.copy(), flat.copy()
+        fp[k] += h
+        fm[k] -= h
+        fd = (R.precond_loss(fp, r, e, levels, base)[0] - R.precond_loss(fm, r, e, levels, base)[0]) / (2 * h)
+        assert abs(g[k] - fd) < 1e-6 * max(1.0, abs(fd)), (k, g[k], fd)
+
+
+def test_unet_layout_counts():
+    # 4 levels, 32 base channels: the parameter count written out by hand
+    ch = [32, 64, 128, 256]
+    n = 9 * (1 * 32 + 32 * 32)
+    n += 9 * (32 * 64 + 64 * 64) + 9 * (64 * 128 + 128 * 128) + 9 * (128 * 256 + 256 * 256)
+    for l in (2, 1, 0):
+        n += 9 * (ch[l + 1] * ch[l] + 2 * ch[l] * ch[l] + ch[l] * ch[l])
+    n += 32
+    assert sum(int(np.prod(s)) for _, s in R.unet_layout(4, 32)) == n
+
+
+def test_preconditioner_is_positively_homogeneous():
+    # no biases and ReLU activations: N(a r) = a N(r) for a > 0, and the
+    # input normalisation makes N exactly invariant in that sense
+    rng = _rng(9)
+    shapes = [s for _, s in R.unet_layout(3, 2)]
+    flat = rng.normal(size=sum(int(np.prod(s)) for s in shapes))
+    r = rng.normal(size=(1, 8, 8))
+    z1 = R.precondition(flat, r, 3, 2)
+    z2 = R.precondition(flat, 7.5 * r, 3, 2)
+    assert np.allclose(z2, 7.5 * z1, rtol=1e-12, atol=1e-12)
+    y, _ = R.unet_forward(flat, 3.0 * r, 3, 2)
+    y1, _ = R.unet_forward(flat, r, 3, 2)
+    assert np.allclose(y, 3.0 * y1, rtol=1e-12, atol=1e-12)
+
+
+def test_adam_first_step_closed_form():
+    # with bias correction the first step is lr * g / (|g| + eps): a sign step
+    rng = _rng(10)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50)
+    p1, m, v = R.adam_step(p, g, np.zeros(50), np.zeros(50), 1, lr=0.01)
+    assert np.allclose(p1 - p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+# --------------------------------------------------------- regulariser, solver
+def test_regulariser_quadratic_form_and_null_space():
+    rng = _rng(11)
+    c = rng.normal(size=(7, 9))
+    q = np.sum(c * R.reg_apply(c, 1.0))
+    ref = np.sum(np.diff(c, axis=0) ** 2) + np.sum(np.diff(c, axis=1) ** 2)
+    assert abs(q - ref) < 1e-10 * ref
+    assert np.allclose(R.reg_apply(np.full((5, 6), 3.0), 2.0), 0.0)
+    d = rng.normal(size=(7, 9))
+    assert abs(np.sum(d * R.reg_apply(c, 1.0)) - np.sum(c * R.reg_apply(d, 1.0))) < 1e-10
+
+
+def test_regulariser_neumann_eigenpairs():
+    # the 1-D Neumann difference Laplacian has the DCT-II vectors as eigenvectors,
+    # eigenvalue 4 sin^2(pi k / (2N)); the 2-D operator adds the two axes
+    ny, nx = 6, 8
+    j = np.arange(ny)[:, None] + 0.5
+    i = np.arange(nx)[None, :] + 0.5
+    for ky, kx in [(0, 1), (2, 0), (3, 5), (5, 7)]:
+        v = np.cos(math.pi * ky * j / ny) * np.cos(math.pi * kx * i / nx)
+        lam = 4 * math.sin(math.pi * ky / (2 * ny)) ** 2 + 4 * math.sin(math.pi * kx / (2 * nx)) ** 2
+        assert np.allclose(R.reg_apply(v, 0.3), 0.3 * lam * v, atol=1e-12)
+
+
+def _tiny_problem(n=1, N=6, seed=12):
+    rng = _rng(seed)
+    th = rng.uniform(0, math.pi, 14).astype(np.float32)
+    y = rng.uniform(-3, 3, 14).astype(np.float32)
+    lc = oracle.lines_from_theta_y(th, y)
+    H = np.stack([oracle.forward(n, np.eye(N * N)[k].reshape(N, N), lc) for k in range(N * N)], axis=1)
+    return lc, H
+
+
+def test_normal_operator_matches_dense_matrix():
+    n, N, lam = 1, 6, 0.05
+    lc, H = _tiny_problem(n, N)
+    Lt = np.stack([R.reg_apply(np.eye(N * N)[k].reshape(N, N), 1.0).ravel() for k in range(N * N)], axis=1)
+    Mdense = H.T @ H + lam * Lt
+    assert np.allclose(Mdense, Mdense.T, atol=1e-10)
+    assert np.min(np.linalg.eigvalsh(Mdense)) > 0
+    c = _rng(13).normal(size=(N, N))
+    assert np.allclose(R.normal_apply(n, c, lc, lam).ravel(), Mdense @ c.ravel(), atol=1e-9)
+
+
+def test_cg_solves_the_dense_system():
+    n, N, lam = 1, 6, 0.05
+    lc, H = _tiny_problem(n, N)
+    b = _rng(14).normal(size=(N, N))
+    x, it, hist = R.cg(lambda v: R.normal_apply(n, v, lc, lam), b, tol=1e-12, maxit=500)
+    Lt = np.stack([R.reg_apply(np.eye(N * N)[k].reshape(N, N), 1.0).ravel() for k in range(N * N)], axis=1)
+    xd = np.linalg.solve(H.T @ H + lam * Lt, b.ravel())
+    assert np.allclose(x.ravel(), xd, rtol=1e-8, atol=1e-8)
+    assert hist[-1] <= 1e-12 and it <= N * N + 20

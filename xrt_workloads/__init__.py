@@ -169,3 +169,88 @@ def large_lines(n_src: int = 1440, n_bins: int = 3072, n_random: int | None = No
 
 def large_phantom(N: int = 2048, seed: int = 5):
     return ellipse_phantom(N, 30, seed=seed, texture_sigma=0.1)
+
+
+# ---------------------------------------------------------------------------
+# Reconstruction inputs (regularised normal equations, learned preconditioner)
+# ---------------------------------------------------------------------------
+
+
+def recon_problem(N: int = 512, n_angles: int = 180, n_bins: int = 768, seed: int = 7):
+    """Ground truth and geometry of the reconstruction workload: an N x N
+    coefficient image (30 ellipses scaled by N/64 plus sigma = 0.1 texture)
+    and parallel-beam lines, n_angles x n_bins at unit spacing."""
+    return parallel_beam(n_angles, n_bins), ellipse_phantom(N, 30, seed, texture_sigma=0.1)
+
+
+def noisy_log_data(clean, photons: float = 1e4, peak: float = 3.0, seed: int = 11):
+    """Measured line integrals under Poisson noise: with kappa scaling the
+    largest clean integral to `peak` attenuation, counts ~ Poisson(I0 exp(-kappa s)),
+    counts of zero clamped to one, p = -ln(counts / I0) / kappa.  float32."""
+    s = np.asarray(clean, dtype=np.float64)
+    smax = float(np.max(np.abs(s)))
+    kappa = peak / smax if smax > 0 else 1.0
+    rng = np.random.default_rng(seed)
+    counts = rng.poisson(photons * np.exp(-kappa * s)).astype(np.float64)
+    counts = np.maximum(counts, 1.0)
+    return (-np.log(counts / photons) / kappa).astype(np.float32)
+
+
+def unet_params(shapes, seed: int):
+    """He-normal draws (std sqrt(2/fan_in); a 1-D shape (an output layer) gets
+    std sqrt(1/fan_in)) for a list of parameter shapes [taps][c_out][c_in] or
+    [c_in], concatenated into one float32 vector."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for shape in shapes:
+        if len(shape) == 1:
+            sd = math.sqrt(1.0 / shape[0])
+        else:
+            sd = math.sqrt(2.0 / (shape[0] * shape[2]))
+        out.append(rng.normal(0.0, sd, size=int(np.prod(shape))))
+    return np.concatenate(out).astype(np.float32)
+
+
+def training_fields(count: int, H: int, W: int, seed: int, device="cpu"):
+    """`count` error images e for (M e, e) training pairs, float32 [count][H][W],
+    each scaled to unit RMS.  Even indices: ellipse phantoms (5-30 ellipses,
+    centres within the grid, semi-axes 2-35% of the size, amplitudes U[-1, 1]);
+    odd indices: Gaussian random fields with power spectrum
+    (|k|^2 + k0^2)^(-alpha), alpha ~ U[0, 2.5], k0 ~ U[0.005, 0.1] cycles per
+    pixel (from white noise to smooth fields).  Drawn with torch on `device`."""
+    import torch
+    dev = torch.device(device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed))
+    out = torch.empty((count, H, W), dtype=torch.float32, device=dev)
+    yy = (torch.arange(H, device=dev, dtype=torch.float32) - 0.5 * (H - 1))[:, None]
+    xx = (torch.arange(W, device=dev, dtype=torch.float32) - 0.5 * (W - 1))[None, :]
+    size = float(min(H, W))
+    ky = torch.fft.fftfreq(H, device=dev)[:, None]
+    kx = torch.fft.rfftfreq(W, device=dev)[None, :]
+    k2 = ky * ky + kx * kx
+
+    def u(*shape, lo=0.0, hi=1.0):
+        return lo + (hi - lo) * torch.rand(*shape, generator=g, device=dev)
+
+    for i in range(count):
+        if i % 2 == 0:
+            E = int(u(1, lo=5, hi=31).item())
+            cx, cy = u(E, lo=-0.45, hi=0.45) * W, u(E, lo=-0.45, hi=0.45) * H
+            a, b = u(E, lo=0.02, hi=0.35) * size, u(E, lo=0.02, hi=0.35) * size
+            th = u(E, hi=math.pi)
+            amp = u(E, lo=-1.0, hi=1.0)
+            c, s = torch.cos(th)[:, None, None], torch.sin(th)[:, None, None]
+            dx, dy = xx[None] - cx[:, None, None], yy[None] - cy[:, None, None]
+            xr, yr = c * dx + s * dy, -s * dx + c * dy
+            inside = (xr / a[:, None, None]) ** 2 + (yr / b[:, None, None]) ** 2 <= 1.0
+            img = (inside.float() * amp[:, None, None]).sum(0)
+        else:
+            alpha = float(u(1, hi=2.5).item())
+            k0 = float(u(1, lo=0.005, hi=0.1).item())
+            noise = torch.randn((H, W), generator=g, device=dev)
+            spec = torch.fft.rfft2(noise) * (k2 + k0 * k0) ** (-alpha / 2.0)
+            img = torch.fft.irfft2(spec, s=(H, W))
+        rms = torch.sqrt(torch.mean(img * img))
+        out[i] = img / rms if float(rms) > 0 else img
+    return out
