@@ -166,11 +166,13 @@ def upsample2_T(g):
 # ---------------------------------------------------------------------------
 
 
-def unet_layout(levels, base):
+def unet_layout(levels, base, max_channels=None):
+    if isinstance(base, tuple):
+        base, max_channels = base
     """Ordered list of (name, shape) of every parameter; the flat parameter
     vector is their concatenation in this order (row-major within each).
 
-    Level l has c_l = base * 2^l channels.  Encoder level l: conv a
+    Level l has c_l = base * 2^l channels, capped at max_channels if given.  Encoder level l: conv a
     (input -> c_l; the input is the 1-channel residual at l = 0, the 2x2
     average pool of level l-1's output otherwise), conv b (c_l -> c_l).
     Decoder level l (from levels-2 down to 0): conv up (c_{l+1} -> c_l, at
@@ -179,7 +181,7 @@ def unet_layout(levels, base):
     conv b (c_l -> c_l).  Every 3x3 convolution is followed by ReLU and has no
     bias.  Output: a 1x1 convolution c_0 -> 1 without activation.
     """
-    ch = [base << l for l in range(levels)]
+    ch = [min(base << l, max_channels or (base << l)) for l in range(levels)]
     out = []
     for l in range(levels):
         cin = 1 if l == 0 else ch[l - 1]
@@ -285,28 +287,28 @@ def unet_backward(flat, cache, gy, levels, base):
     return pack(g, levels, base)
 
 
-def precondition(flat, r, levels, base):
+def precondition(flat, r, levels, base, gain=1.0):
     """The learned preconditioner z = N(r) for a batch r [B][H][W]:
-    N(r) = UNet(r / rms(r)) * rms(r) per image (rms over its pixels)."""
+    N(r) = gain * rms(r) * UNet(r / rms(r)) per image (rms over its pixels)."""
     r = np.asarray(r, dtype=np.float64)
     rms = np.sqrt(np.mean(r * r, axis=(1, 2)))
     y, _ = unet_forward(flat, r / rms[:, None, None], levels, base)
-    return y * rms[:, None, None]
+    return gain * y * rms[:, None, None]
 
 
-def precond_loss(flat, r, e, levels, base):
+def precond_loss(flat, r, e, levels, base, gain=1.0):
     """Training loss for pairs (r = M e, e) and its gradient.
 
     loss = mean_b ||N(r_b) - e_b||^2 / ||e_b||^2.  With s = 1/rms(r_b) this is
-    ||UNet(s r_b) - s e_b||^2 / ||s e_b||^2, which is how it is evaluated.
-    Returns (loss, gradient w.r.t. the flat parameters).
+    ||UNet(s r_b) - s e_b / gain||^2 / ||s e_b / gain||^2, which is how it is
+    evaluated.  Returns (loss, gradient w.r.t. the flat parameters).
     """
     r = np.asarray(r, dtype=np.float64)
     e = np.asarray(e, dtype=np.float64)
     B = r.shape[0]
     s = 1.0 / np.sqrt(np.mean(r * r, axis=(1, 2)))
     y, cache = unet_forward(flat, r * s[:, None, None], levels, base)
-    t = e * s[:, None, None]
+    t = e * s[:, None, None] / gain
     tn = np.sum(t * t, axis=(1, 2))
     diff = y - t
     loss = float(np.mean(np.sum(diff * diff, axis=(1, 2)) / tn))

@@ -25,10 +25,14 @@ XRT_EPLAN = -6
 XRT_LINES_THETA_Y = 0
 XRT_LINES_ENDPOINTS = 1
 
-# every symbol declared in include/xrt.h
+# every symbol declared in include/xrt.h and include/xrt_learn.h
 EXPORTS = ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
            "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_plan_destroy",
-           "xrt_status_string", "xrt_last_error", "xrt_version")
+           "xrt_status_string", "xrt_last_error", "xrt_version",
+           "xrt_reg_apply", "xrt_normal_apply", "xrt_unet_create", "xrt_unet_destroy",
+           "xrt_unet_num_params", "xrt_unet_set_params", "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_get_params", "xrt_unet_apply",
+           "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
+           "xrt_unet_train_step_normal", "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve")
 
 
 class XrtGrid(ctypes.Structure):
@@ -40,6 +44,13 @@ class XrtLines(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("theta", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("endpoints", ctypes.c_void_p)]
+
+
+class XrtSolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("operator_applies", ctypes.c_int32),
+                ("learned_accepted", ctypes.c_int32), ("learned_rejected", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double)]
 
 
 class XrtError(RuntimeError):
@@ -77,8 +88,34 @@ def load() -> ctypes.CDLL:
     lib.xrt_last_error.argtypes = []
     lib.xrt_last_error.restype = ctypes.c_char_p
     lib.xrt_version.restype = ctypes.c_char_p
+    f32, u64 = ctypes.c_float, ctypes.c_uint64
+    lib.xrt_reg_apply.argtypes = [vp, i32, i32, f32, vp, vp]
+    lib.xrt_normal_apply.argtypes = [vp, f32, vp, vp, vp, vp]
+    lib.xrt_unet_create.argtypes = [i32, i32, i32, i32, i32, i32, u64, ctypes.POINTER(vp)]
+    lib.xrt_unet_destroy.argtypes = [vp]
+    lib.xrt_unet_destroy.restype = None
+    lib.xrt_unet_num_params.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.xrt_unet_set_params.argtypes = [vp, vp, vp]
+    lib.xrt_unet_get_params.argtypes = [vp, vp, vp]
+    lib.xrt_unet_set_gain.argtypes = [vp, f32]
+    lib.xrt_unet_get_gain.argtypes = [vp, ctypes.POINTER(f32)]
+    lib.xrt_unet_set_relu.argtypes = [vp, i32]
+    lib.xrt_unet_apply.argtypes = [vp, vp, vp, i32, vp]
+    lib.xrt_unet_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.xrt_unet_train_step.argtypes = [vp, vp, vp, i32, f32, vp, vp]
+    lib.xrt_unet_loss_grad_normal.argtypes = [vp, vp, f32, vp, i32, vp, vp, vp]
+    lib.xrt_unet_train_step_normal.argtypes = [vp, vp, f32, vp, i32, f32, vp, vp]
+    lib.xrt_conv3x3_forward.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp]
+    lib.xrt_conv3x3_grad_input.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
+    lib.xrt_conv3x3_grad_weight.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
+    lib.xrt_solve.argtypes = [vp, f32, vp, vp, f32, i32, vp, i32, ctypes.POINTER(XrtSolveInfo),
+                              ctypes.POINTER(ctypes.c_double), i32, vp]
     for name in ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
-                 "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz"):
+                 "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_reg_apply",
+                 "xrt_normal_apply", "xrt_unet_create", "xrt_unet_num_params",
+                 "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_apply",
+                 "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
+                 "xrt_unet_train_step_normal", "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -146,3 +183,92 @@ def xrt_last_error() -> str:
 
 def xrt_version() -> str:
     return load().xrt_version().decode()
+
+
+# ---------------------------------------------------------- include/xrt_learn.h
+def xrt_reg_apply(c, nx, ny, lam, out, stream) -> int:
+    return load().xrt_reg_apply(c, int(nx), int(ny), float(lam), out, stream)
+
+
+def xrt_normal_apply(plan, lam, c, out, sino_ws, stream) -> int:
+    return load().xrt_normal_apply(plan, float(lam), c, out, sino_ws, stream)
+
+
+def xrt_unet_create(levels, base, max_channels, height, width, max_batch, seed):
+    out = ctypes.c_void_p()
+    st = load().xrt_unet_create(int(levels), int(base), int(max_channels), int(height), int(width),
+                                int(max_batch), int(seed), ctypes.byref(out))
+    return st, out.value
+
+
+def xrt_unet_destroy(net) -> None:
+    load().xrt_unet_destroy(net)
+
+
+def xrt_unet_num_params(net):
+    a = ctypes.c_int64()
+    st = load().xrt_unet_num_params(net, ctypes.byref(a))
+    return st, a.value
+
+
+def xrt_unet_set_params(net, params, stream) -> int:
+    return load().xrt_unet_set_params(net, params, stream)
+
+
+def xrt_unet_get_params(net, params, stream) -> int:
+    return load().xrt_unet_get_params(net, params, stream)
+
+
+def xrt_unet_set_gain(net, gain) -> int:
+    return load().xrt_unet_set_gain(net, float(gain))
+
+
+def xrt_unet_set_relu(net, on) -> int:
+    return load().xrt_unet_set_relu(net, int(on))
+
+
+def xrt_unet_get_gain(net):
+    g = ctypes.c_float()
+    st = load().xrt_unet_get_gain(net, ctypes.byref(g))
+    return st, g.value
+
+
+def xrt_unet_apply(net, r, z, batch, stream) -> int:
+    return load().xrt_unet_apply(net, r, z, int(batch), stream)
+
+
+def xrt_unet_loss_grad(net, r, e, batch, loss, grad, stream) -> int:
+    return load().xrt_unet_loss_grad(net, r, e, int(batch), loss, grad, stream)
+
+
+def xrt_unet_train_step(net, r, e, batch, lr, loss, stream) -> int:
+    return load().xrt_unet_train_step(net, r, e, int(batch), float(lr), loss, stream)
+
+
+def xrt_unet_loss_grad_normal(net, plan, lam, r, batch, loss, grad, stream) -> int:
+    return load().xrt_unet_loss_grad_normal(net, plan, float(lam), r, int(batch), loss, grad, stream)
+
+
+def xrt_unet_train_step_normal(net, plan, lam, r, batch, lr, loss, stream) -> int:
+    return load().xrt_unet_train_step_normal(net, plan, float(lam), r, int(batch), float(lr), loss, stream)
+
+
+def xrt_conv3x3_forward(x, w, B, H, W, cin, cout, relu, y, stream) -> int:
+    return load().xrt_conv3x3_forward(x, w, int(B), int(H), int(W), int(cin), int(cout), int(relu), y,
+                                      stream)
+
+
+def xrt_conv3x3_grad_input(gy, w, B, H, W, cin, cout, gx, stream) -> int:
+    return load().xrt_conv3x3_grad_input(gy, w, int(B), int(H), int(W), int(cin), int(cout), gx, stream)
+
+
+def xrt_conv3x3_grad_weight(x, gy, B, H, W, cin, cout, gw, stream) -> int:
+    return load().xrt_conv3x3_grad_weight(x, gy, int(B), int(H), int(W), int(cin), int(cout), gw, stream)
+
+
+def xrt_solve(plan, lam, b, x, tol, maxit, net, window, history_cap, stream):
+    info = XrtSolveInfo()
+    hist = (ctypes.c_double * max(1, int(history_cap)))()
+    st = load().xrt_solve(plan, float(lam), b, x, float(tol), int(maxit), net, int(window), ctypes.byref(info),
+                          hist if history_cap > 0 else None, int(history_cap), stream)
+    return st, info, [hist[i] for i in range(min(int(history_cap), info.iterations))]

@@ -1,5 +1,6 @@
 // Host side of libxrt.so: argument checks, plan construction, dispatch, and
 // the FP64 construction of the knot-transition table used by the kernels.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
@@ -139,7 +140,7 @@ struct Allocs {
 void free_plan_memory(xrt_plan* p, hipStream_t s)
 {
     void* ptrs[] = {p->xc, p->kap, p->idx, p->off, p->hdr, p->tab,
-                    p->cv, p->dv, p->ch, p->dh, p->sw, p->part};
+                    p->cv, p->dv, p->ch, p->dh, p->sw, p->part, p->adj_part};
     for (void* q : ptrs)
         if (q) (void)hipFreeAsync(q, s);
 }
@@ -147,6 +148,8 @@ void free_plan_memory(xrt_plan* p, hipStream_t s)
 }  // namespace
 
 namespace xrt {
+void set_last_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
 const float* etable_host(int n, int* n_entries)
 {
     std::call_once(g_tab_once, build_tables);
@@ -224,7 +227,21 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     p->ch = al.get<float>((size_t)g.nx * p->pitch_h);
     p->dh = al.get<float>((size_t)g.nx * p->pitch_h);
     p->sw = al.get<float>(m);
-    p->part = al.get<double>(m);
+    // Small grids: one orientation's layouts fit in L2, so all its strips can
+    // run in one launch (more lines in flight) with a partial sum per strip.
+    // Large grids keep the strip-by-strip schedule and one running sum.
+    {
+        const int ns = std::max(p->strips_v, p->strips_h);
+        const size_t lay = (size_t)std::max((int64_t)g.ny * p->pitch_v, (int64_t)g.nx * p->pitch_h) * 2 * sizeof(float);
+        p->fwd_conc = (ns > 1 && lay <= ((size_t)4 << 20) && (size_t)ns * (size_t)m * sizeof(double) <= ((size_t)256 << 20))
+                          ? 1 : 0;
+        p->part = al.get<double>(p->fwd_conc ? (size_t)ns * m : (size_t)m);
+        // few adjoint tiles: split each tile's candidate lines over several
+        // workgroups (partial images, summed in a fixed order)
+        const int64_t tiles = (int64_t)((g.nx + kTileI - 1) / kTileI) * ((g.ny + kTileJ - 1) / kTileJ);
+        p->adj_split = tiles >= 1024 ? 1 : (int)std::min<int64_t>(8, (1024 + tiles - 1) / tiles);
+        p->adj_part = p->adj_split > 1 ? al.get<float>((size_t)p->adj_split * g.nx * g.ny) : nullptr;
+    }
     // temporaries
     uint32_t* key = al.get<uint32_t>(m);
     double* xc_in = al.get<double>(m);

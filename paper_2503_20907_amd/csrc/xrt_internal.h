@@ -101,6 +101,11 @@ const float* etable_host(int n, int* n_entries);
 
 }  // namespace xrt
 
+namespace xrt {
+// message returned by xrt_last_error() on this thread
+void set_last_error(const char* msg);
+}  // namespace xrt
+
 struct xrt_plan;
 struct xrt_plan {
     uint64_t magic;
@@ -122,6 +127,9 @@ struct xrt_plan {
     int pitch_v, pitch_h;
     float *cv, *dv, *ch, *dh;  // coefficient / difference layouts
     float* sw;                 // sinogram in sorted order, scaled
-    double* part;              // forward sums over strips, [m]
+    double* part;              // forward sums over strips: [m], or [strips][m] when fwd_conc
     int strips_v, strips_h;    // strips of kStrip rows, per orientation
+    int fwd_conc;              // 1: the strips of an orientation run in one launch
+    int adj_split;             // workgroups sharing one adjoint tile's candidate lines
+    float* adj_part;           // [adj_split][ny][nx] partial images (adj_split > 1)
 };

@@ -481,9 +481,10 @@ struct FwdArgs {
     int nx, ny;
     double h;
     float* sino;
-    double* part;  // [m] sums over the strips done so far
+    double* part;  // [m] sums over the strips done so far, or [strips][m] (concurrent)
     int strips_v, strips_h;
-    int strip;     // strip of this launch
+    int strip;     // strip of this launch (sequential schedule)
+    int concurrent;  // 1: blockIdx.x / nblk_pad is the strip; each strip writes its own partials
     int nblk, nblk_pad;
 };
 
@@ -533,8 +534,13 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
     __syncthreads();
 
-    const int strip = A.strip;
-    const int bid = blockIdx.x;
+    int strip = A.strip;
+    int bid = blockIdx.x;
+    if (A.concurrent) {
+        strip = blockIdx.x / A.nblk_pad;
+        bid = blockIdx.x - strip * A.nblk_pad;
+        if (strip >= (VERT ? A.strips_v : A.strips_h)) return;
+    }
     const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
     // vertical lines are the sorted range [0, m_vert), horizontal ones
     // [m_vert, m_valid).  The grid covers all m lines; the blocks of this
@@ -567,7 +573,8 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
         else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
         else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
     }
-    if (strip == 0) A.part[k] = (double)acc;
+    if (A.concurrent) A.part[(int64_t)strip * A.m + k] = (double)acc;
+    else if (strip == 0) A.part[k] = (double)acc;
     else if (ja <= jb) A.part[k] += (double)acc;
 }
 
@@ -581,7 +588,11 @@ __global__ void __launch_bounds__(kBlock) k_fwd_reduce(FwdArgs A)
     const int64_t m_valid = A.hdr->m_valid;
     float v = 0.f;
     if (k < m_valid) {
-        const double acc = A.part[k];
+        double acc = A.part[k];
+        if (A.concurrent) {
+            const int ns = k < A.hdr->m_vert ? A.strips_v : A.strips_h;
+            for (int st = 1; st < ns; ++st) acc += A.part[(int64_t)st * A.m + k];
+        }
         const double kap = A.kap[k];
         v = (float)(acc * A.h * sqrt(1.0 + kap * kap) / (double)tap_scale<N>());
     }
@@ -622,6 +633,8 @@ struct AdjArgs {
     int nbk_v, nbk_h, boff_v, boff_h;
     int tiles_i, tiles_j;
     int ntiles, ntiles_pad;
+    int split;     // workgroups per tile (blockIdx.y): chunk c goes to workgroup c % split
+    float* part;   // [split][ny][nx] partial images when split > 1
     float* out;
 };
 
@@ -821,7 +834,7 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
         __syncthreads();
         const uint32_t total = s_pre[kSlopeBins];
 
-        for (uint32_t base = 0; base < total; base += 2 * kBlock) {
+        for (uint32_t base = blockIdx.y * 2u * kBlock; base < total; base += (uint32_t)A.split * 2u * kBlock) {
             uint32_t kk[2] = {0, 0};
             float svv[2] = {0.f, 0.f};
 #pragma unroll
@@ -876,8 +889,21 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
         const int p = tid + e * kBlock;
         const int pj = p / kTileI, pi = p % kTileI;
         const int i = i0 + pi, j = j0 + pj;
-        if (i < A.nx && j < A.ny) A.out[(int64_t)j * A.nx + i] = o[e];
+        if (i < A.nx && j < A.ny) {
+            if (A.split > 1) A.part[((int64_t)blockIdx.y * A.ny + j) * A.nx + i] = o[e];
+            else A.out[(int64_t)j * A.nx + i] = o[e];
+        }
     }
+}
+
+// out = sum over the split workgroups' partial images, in a fixed order
+__global__ void __launch_bounds__(kBlock) k_adj_reduce(const float* part, int split, int64_t npix, float* out)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= npix) return;
+    float v = part[k];
+    for (int g = 1; g < split; ++g) v += part[(int64_t)g * npix + k];
+    out[k] = v;
 }
 
 // ---------------------------------------------------------------- nnz
@@ -1022,6 +1048,18 @@ static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
     // launch's range return at once
     a.nblk = (int)((p->m + kBlock - 1) / kBlock);
     a.nblk_pad = (a.nblk + 7) / 8 * 8;
+    a.concurrent = p->fwd_conc;
+    a.strip = 0;
+    if (p->fwd_conc) {
+        hipLaunchKernelGGL((k_forward<N, true>), dim3((unsigned)(a.nblk_pad * p->strips_v)), dim3(kBlock), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_forward<N, false>), dim3((unsigned)(a.nblk_pad * p->strips_h)), dim3(kBlock), 0, s, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fwd_reduce<N>, dim3((unsigned)a.nblk), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
     const int ns = p->strips_v > p->strips_h ? p->strips_v : p->strips_h;
     for (int st = 0; st < ns; ++st) {
         a.strip = st;
@@ -1074,7 +1112,14 @@ static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
     a.ntiles = a.tiles_i * a.tiles_j;
     a.ntiles_pad = (a.ntiles + 7) / 8 * 8;
     a.out = out;
-    hipLaunchKernelGGL(k_adjoint<N>, dim3((unsigned)a.ntiles_pad), dim3(kBlock), 0, s, a);
+    a.split = p->adj_split;
+    a.part = p->adj_part;
+    hipLaunchKernelGGL(k_adjoint<N>, dim3((unsigned)a.ntiles_pad, (unsigned)a.split), dim3(kBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.split == 1) return e;
+    const int64_t npix = (int64_t)p->g.nx * p->g.ny;
+    hipLaunchKernelGGL(k_adj_reduce, dim3((unsigned)((npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.part,
+                       a.split, npix, out);
     return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
 """Host-side tests of the C ABI: the library loads without a GPU, exports every
-symbol include/xrt.h declares, and rejects bad arguments synchronously,
+symbol include/*.h declares, and rejects bad arguments synchronously,
 before any HIP call."""
 import ctypes
 import os
@@ -13,15 +13,19 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    txt = open(os.path.join(ROOT, "include", "xrt.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(xrt_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(xrt_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     lib = L.load()
     names = header_functions()
-    assert len(names) >= 11
+    assert len(names) >= 30
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(L.EXPORTS) == names
@@ -107,3 +111,35 @@ def test_product_path_has_no_cpu_fallback():
     from paper_2503_20907_amd import ops
     with pytest.raises(ValueError):
         ops.forward(torch.zeros(4, 4), ops.Lines(theta=[0.0], y=[0.0], device="cpu"), 1)
+
+
+# ------------------------------------------------------------ include/xrt_learn.h
+def test_learn_entry_points_reject_bad_arguments():
+    lib = L.load()
+    out = ctypes.c_void_p()
+    # levels, base, channel cap, image size: rejected before any allocation
+    assert lib.xrt_unet_create(1, 32, 0, 64, 64, 1, 0, ctypes.byref(out)) == L.XRT_EINVAL
+    assert lib.xrt_unet_create(4, 48, 0, 64, 64, 1, 0, ctypes.byref(out)) == L.XRT_EINVAL
+    assert lib.xrt_unet_create(4, 32, 16, 64, 64, 1, 0, ctypes.byref(out)) == L.XRT_EINVAL
+    assert lib.xrt_unet_create(4, 32, 0, 60, 64, 1, 0, ctypes.byref(out)) == L.XRT_ESIZE
+    assert lib.xrt_unet_create(4, 32, 0, 64, 64, 0, 0, ctypes.byref(out)) == L.XRT_ESIZE
+    assert lib.xrt_unet_create(4, 32, 0, 64, 64, 1, 0, None) == L.XRT_EINVAL
+    assert out.value is None
+    # operations on a null network / plan
+    assert lib.xrt_unet_apply(None, 1, 1, 1, None) == L.XRT_EINVAL
+    assert lib.xrt_unet_set_gain(None, ctypes.c_float(1.0)) == L.XRT_EINVAL
+    assert lib.xrt_unet_set_relu(None, 1) == L.XRT_EINVAL
+    n = ctypes.c_int64()
+    assert lib.xrt_unet_num_params(None, ctypes.byref(n)) == L.XRT_EINVAL
+    assert lib.xrt_reg_apply(None, 8, 8, ctypes.c_float(1.0), 1, None) == L.XRT_EINVAL
+    assert lib.xrt_reg_apply(1, 0, 8, ctypes.c_float(1.0), 1, None) == L.XRT_EINVAL
+    assert lib.xrt_normal_apply(None, ctypes.c_float(1.0), 1, 1, None, None) == L.XRT_EPLAN
+    info = L.XrtSolveInfo()
+    assert lib.xrt_solve(None, ctypes.c_float(1.0), 1, 1, ctypes.c_float(1e-3), 10, None, 1,
+                         ctypes.byref(info), None, 0, None) == L.XRT_EPLAN
+    assert lib.xrt_solve(1, ctypes.c_float(1.0), 1, 1, ctypes.c_float(0.0), 10, None, 1,
+                         ctypes.byref(info), None, 0, None) == L.XRT_EINVAL
+    # convolutions need channel counts that are multiples of 32
+    assert lib.xrt_conv3x3_forward(1, 1, 1, 8, 8, 16, 32, 0, 1, None) == L.XRT_EINVAL
+    assert lib.xrt_conv3x3_grad_weight(1, 1, 1, 8, 8, 32, 48, 1, None) == L.XRT_EINVAL
+    assert lib.xrt_conv3x3_grad_input(None, 1, 1, 8, 8, 32, 32, 1, None) == L.XRT_EINVAL

@@ -1,0 +1,222 @@
+"""GPU parity of the reconstruction / learned-preconditioner kernels against
+the FP64 oracle (oracle/recon.py), through the C ABI.
+
+Tolerances:
+* 3x3 convolution, its input gradient and weight gradient: bf16 operands are
+  exact in fp32 products and accumulated in fp32 over <= 9*256 terms (input
+  gradient) or the pixel count (weight gradient), so the relative L2 error
+  against FP64 on the same bf16 values is O(sqrt(K) 2^-24) ~ 1e-6: gate 2e-5.
+* Whole network: every activation and activation gradient is rounded to bf16
+  (2^-9 relative) and the weights are bf16 copies, so output and gradient
+  agree with the FP64 network (on the same bf16-rounded weights) to ~1e-2
+  relative L2; gate 4e-2 with cosine similarity >= 0.999.
+* Normal operator: fp32 transform (<= 1e-6, see the transform's parity
+  tests) plus the fp32 regulariser: gate 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.recon as R
+import xrt_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def learn():
+    from paper_2503_20907_amd import learn
+    return learn
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def bf(t, dev):
+    return torch.as_tensor(t, dtype=torch.float32).to(torch.bfloat16).to(dev).contiguous()
+
+
+# ---------------------------------------------------------------- convolution
+CONV_CASES = [
+    (2, 7, 70, 32, 32),      # ragged rows and a second, partial tile column
+    (1, 9, 33, 64, 32),
+    (2, 5, 64, 32, 64),
+    (1, 12, 20, 128, 256),
+    (3, 64, 64, 64, 64),     # wide-output variant (enough tiles)
+]
+
+
+@pytest.mark.parametrize("B,H,Wd,cin,cout", CONV_CASES)
+def test_conv3x3_forward_matches_oracle(dev, learn, B, H, Wd, cin, cout):
+    print(f"conv fwd B={B} H={H} W={Wd} cin={cin} cout={cout}", flush=True)
+    g = torch.Generator().manual_seed(B * 1000 + H * 10 + cin)
+    x = bf(torch.randn(B, H, Wd, cin, generator=g), dev)
+    w = bf(torch.randn(9, cout, cin, generator=g) / math.sqrt(9 * cin), dev)
+    y = learn.conv3x3_forward(x, w).cpu().numpy()
+    ref = R.conv3x3(x.float().cpu().numpy(), w.float().cpu().numpy())
+    assert rel(y, ref) < 2e-5
+    yr = learn.conv3x3_forward(x, w, relu=True).cpu().numpy()
+    assert rel(yr, np.maximum(ref, 0)) < 2e-5
+
+
+@pytest.mark.parametrize("B,H,Wd,cin,cout", CONV_CASES)
+def test_conv3x3_grad_input_matches_oracle(dev, learn, B, H, Wd, cin, cout):
+    print(f"conv dgrad B={B} H={H} W={Wd} cin={cin} cout={cout}", flush=True)
+    g = torch.Generator().manual_seed(B * 1000 + H * 10 + cout + 1)
+    gy = bf(torch.randn(B, H, Wd, cout, generator=g), dev)
+    w = bf(torch.randn(9, cout, cin, generator=g) / math.sqrt(9 * cout), dev)
+    gx = learn.conv3x3_grad_input(gy, w).cpu().numpy()
+    ref = R.conv3x3_grad_input(gy.float().cpu().numpy(), w.float().cpu().numpy())
+    assert rel(gx, ref) < 2e-5
+
+
+@pytest.mark.parametrize("B,H,Wd,cin,cout", CONV_CASES + [(2, 130, 150, 32, 32)])
+def test_conv3x3_grad_weight_matches_oracle(dev, learn, B, H, Wd, cin, cout):
+    print(f"conv wgrad B={B} H={H} W={Wd} cin={cin} cout={cout}", flush=True)
+    g = torch.Generator().manual_seed(B * 1000 + H * 10 + cin + 2)
+    x = bf(torch.randn(B, H, Wd, cin, generator=g), dev)
+    gy = bf(torch.randn(B, H, Wd, cout, generator=g), dev)
+    gw = learn.conv3x3_grad_weight(x, gy).cpu().numpy()
+    ref = R.conv3x3_grad_weight(x.float().cpu().numpy(), gy.float().cpu().numpy())
+    assert rel(gw, ref) < 2e-5
+
+
+def test_conv3x3_rejects_bad_channels(dev, learn):
+    from paper_2503_20907_amd import _lib
+    x = bf(torch.zeros(1, 4, 4, 16), dev)
+    w = bf(torch.zeros(9, 32, 16), dev)
+    with pytest.raises(_lib.XrtError):
+        learn.conv3x3_forward(x, w)
+
+
+# --------------------------------------------------------------------- U-Net
+def _bf16_round(a):
+    return torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("levels,H,Wd,B", [(3, 16, 24, 2), (4, 32, 32, 1)])
+def test_unet_loss_and_gradient_match_oracle(dev, learn, levels, H, Wd, B):
+    print(f"unet grad levels={levels} {H}x{Wd} B={B}", flush=True)
+    base = 32
+    shapes = [s for _, s in R.unet_layout(levels, base)]
+    p = W.unet_params(shapes, seed=21)
+    net = learn.UNet(H, Wd, levels=levels, base=base, max_batch=B, seed=0)
+    assert net.num_params == p.size
+    net.set_params(torch.as_tensor(p, device=dev))
+    fields = W.training_fields(2 * B, H, Wd, seed=22)
+    r = fields[:B].numpy().astype(np.float32)
+    e = fields[B:].numpy().astype(np.float32)
+    loss, grad = net.loss_grad(torch.as_tensor(r, device=dev), torch.as_tensor(e, device=dev))
+    loss_ref, grad_ref = R.precond_loss(_bf16_round(p), r, e, levels, base)
+    assert abs(float(loss) - loss_ref) < 2e-2 * loss_ref
+    g = grad.cpu().numpy()
+    assert rel(g, grad_ref) < 4e-2
+    cos = float(np.dot(g, grad_ref) / (np.linalg.norm(g) * np.linalg.norm(grad_ref)))
+    assert cos > 0.999
+    z = net.apply(torch.as_tensor(r, device=dev)).cpu().numpy()
+    zref = R.precondition(_bf16_round(p), r, levels, base)
+    assert rel(z, zref) < 4e-2
+    net.close()
+
+
+def test_unet_zero_residual_maps_to_zero(dev, learn):
+    net = learn.UNet(16, 16, levels=3, base=32, max_batch=1, seed=3)
+    z = net.apply(torch.zeros(16, 16, device=dev))
+    assert torch.all(z == 0)
+    net.close()
+
+
+def test_unet_train_step_is_an_adam_sign_step(dev, learn):
+    # first Adam step from zero state moves every parameter by lr * g/(|g|+eps),
+    # i.e. by -lr sign(g) where |g| >> eps; the sign is checked against the
+    # FP64 oracle gradient where the two gradients agree clearly
+    levels, base, H = 3, 32, 16
+    shapes = [s for _, s in R.unet_layout(levels, base)]
+    p = W.unet_params(shapes, seed=31)
+    net = learn.UNet(H, H, levels=levels, base=base, max_batch=2, seed=0)
+    net.set_params(torch.as_tensor(p, device=dev))
+    f = W.training_fields(4, H, H, seed=32)
+    r, e = f[:2].numpy(), f[2:].numpy()
+    lr = 1e-3
+    net.train_step(torch.as_tensor(r, device=dev), torch.as_tensor(e, device=dev), lr)
+    p1 = net.get_params().cpu().numpy().astype(np.float64)
+    _, gref = R.precond_loss(_bf16_round(p), r, e, levels, base)
+    step = p1 - p.astype(np.float64)
+    big = np.abs(gref) > 0.2 * np.abs(gref).max() * 0.1
+    assert big.sum() > 100
+    assert np.all(np.sign(step[big]) == -np.sign(gref[big]))
+    assert np.allclose(np.abs(step[big]), lr, rtol=1e-3)
+    net.close()
+
+
+# ------------------------------------------------------- regulariser, solver
+def test_reg_apply_matches_oracle(dev, learn):
+    c = np.random.default_rng(41).normal(size=(37, 53)).astype(np.float32)
+    out = learn.reg_apply(torch.as_tensor(c, device=dev), 0.3).cpu().numpy()
+    assert rel(out, R.reg_apply(c, 0.3)) < 1e-6
+
+
+@pytest.fixture(scope="module")
+def small_recon(dev):
+    from paper_2503_20907_amd import ops
+    N, n, lam = 64, 3, 1e-2
+    spec = W.parallel_beam(45, 96)
+    c_true = W.ellipse_phantom(N, 10, seed=42)
+    lc = oracle.lines(spec)
+    p = W.noisy_log_data(oracle.forward(n, c_true, lc), seed=43)
+    b = oracle.adjoint(n, p.astype(np.float64), lc, N, N)
+    plan = ops.Plan(N, N, n, ops.Lines.from_spec(spec))
+    return {"N": N, "n": n, "lam": lam, "lc": lc, "b": b, "plan": plan}
+
+
+def test_normal_apply_matches_oracle(dev, learn, small_recon):
+    s = small_recon
+    c = np.random.default_rng(44).normal(size=(s["N"], s["N"])).astype(np.float32)
+    out = learn.normal_apply(s["plan"], torch.as_tensor(c, device=dev), s["lam"]).cpu().numpy()
+    assert rel(out, R.normal_apply(s["n"], c, s["lc"], s["lam"])) < 1e-5
+
+
+@pytest.mark.parametrize("use_net", [False, True])
+def test_solver_reaches_tolerance_by_oracle_residual(dev, learn, small_recon, use_net):
+    s = small_recon
+    net = learn.UNet(s["N"], s["N"], levels=3, base=32, max_batch=1, seed=5) if use_net else None
+    b = torch.as_tensor(s["b"].astype(np.float32), device=dev)
+    x, info = learn.solve(s["plan"], b, s["lam"], tol=1e-3, maxit=3000, net=net, history=4000)
+    assert info["converged"]
+    xo = x.cpu().numpy().astype(np.float64)
+    bo = s["b"].astype(np.float32).astype(np.float64)
+    res = np.linalg.norm(bo - R.normal_apply(s["n"], xo, s["lc"], s["lam"])) / np.linalg.norm(bo)
+    assert res <= 1.02e-3, res
+    assert abs(res - info["rel_residual"]) < 5e-5
+    if use_net:
+        assert info["learned_accepted"] + info["learned_rejected"] >= info["iterations"]
+        net.close()
+
+
+def test_cg_iterates_match_oracle_cg(dev, learn, small_recon):
+    # While the residual is still large the GPU's CG residual history follows
+    # the FP64 oracle's CG to near fp32 accuracy.  Later steps are gated
+    # loosely: once ||r|| falls to ~1e-2 ||b||, the fp32 operator's ~1e-6 ||b||
+    # error is ~1e-4 of ||r|| and CG amplifies it.
+    s = small_recon
+    b = torch.as_tensor(s["b"].astype(np.float32), device=dev)
+    _, info = learn.solve(s["plan"], b, s["lam"], tol=1e-30, maxit=8, history=8)
+    bo = s["b"].astype(np.float32).astype(np.float64)
+    _, it, hist = R.cg(lambda v: R.normal_apply(s["n"], v, s["lc"], s["lam"]), bo, tol=1e-30, maxit=8)
+    assert it == 8 and len(info["history"]) == 8
+    g, o = np.array(info["history"]), np.array(hist[1:])
+    msg = f"gpu {g.tolist()} oracle {o.tolist()}"
+    assert np.allclose(g[:5], o[:5], rtol=1e-4, atol=0), msg
+    assert np.allclose(g, o, rtol=5e-2, atol=0), msg
