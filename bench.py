@@ -6,7 +6,12 @@ One step = xrt_plan_forward + xrt_plan_adjoint over the whole line list (the
 plan is built once, before timing; its build time is reported separately).
 Inputs are device-resident when timing starts.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+The line also carries "recon": time to relative residual 1e-3 of the
+Tikhonov normal equations (lambda 1e-2) on a 512 x 512 cubic grid with
+180 x 768 parallel-beam Poisson-noisy data, plain CG against flexible CG with
+the trained U-Net preconditioner (training time reported separately).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--no-recon]
 """
 from __future__ import annotations
 
@@ -85,12 +90,82 @@ def cpu_baseline(spec, coeffs, degree, n_lines_total, seconds_target=15.0):
             "lines_per_s": rate}
 
 
+def recon_leg(log):
+    """Metric 2: wall time to ||b - M x|| <= 1e-3 ||b|| from x = 0."""
+    import numpy as np
+    import torch
+
+    import xrt_workloads as W
+    from paper_2503_20907_amd import learn, ops
+    dev = torch.device("cuda:0")
+    N, n, lam, tol = 512, 3, 1e-2, 1e-3
+    spec, c_true = W.recon_problem(N, 180, 768)
+    plan = ops.Plan(N, N, n, ops.Lines.from_spec(spec))
+    clean = plan.forward(torch.as_tensor(c_true, device=dev)).cpu().numpy()
+    p = torch.as_tensor(W.noisy_log_data(clean, photons=1e4, peak=3.0), device=dev)
+    b = plan.adjoint(p)
+
+    def timed(reps=3, **kw):
+        out = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = learn.solve(plan, b, lam, tol=tol, maxit=2000, **kw)
+            torch.cuda.synchronize()
+            out.append(((time.perf_counter() - t0) * 1e3, info))
+        out.sort(key=lambda v: v[0])
+        return out[len(out) // 2]
+
+    cg_ms, cg = timed()
+    log(f"[bench] recon CG {cg_ms:.2f} ms, {cg['iterations']} steps")
+    fields = W.training_fields(800, N, N, seed=3, device=dev)
+    net, st = learn.train_preconditioner(plan, lam, fields, levels=6, base=32, max_channels=256, steps=4000,
+                                         rounds=5, refresh=400, seed=1)
+    log(f"[bench] recon training {st['train_s']:.1f} s")
+    window, period = 8, 4
+    ln_ms, ln = timed(net=net, window=window, period=period)
+    log(f"[bench] recon learned {ln_ms:.2f} ms, {ln['iterations']} steps")
+    z = torch.empty_like(b)
+    for _ in range(3):
+        net.apply(b, z)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        net.apply(b, z)
+    torch.cuda.synchronize()
+    net_ms = (time.perf_counter() - t0) * 100.0
+    q = torch.empty_like(b)
+    ws = torch.empty(plan.lines.n, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        learn.normal_apply(plan, b, lam, out=q, sino_ws=ws)
+    torch.cuda.synchronize()
+    op_ms = (time.perf_counter() - t0) * 100.0
+    net.close()
+    plan.close()
+    return {"metric": "wall ms to relative residual 1e-3, learned vs CG",
+            "workload": "512x512 cubic B-spline, 180x768 parallel beam, Poisson I0=1e4, lambda=1e-2, x0=0",
+            "cg_ms": round(cg_ms, 3), "cg_steps": cg["iterations"],
+            "cg_operator_applies": cg["operator_applies"],
+            "learned_ms": round(ln_ms, 3), "learned_steps": ln["iterations"],
+            "learned_operator_applies": ln["operator_applies"],
+            "learned_network_steps": ln["learned_accepted"], "learned_rejected": ln["learned_rejected"],
+            "learned_over_cg_time": round(ln_ms / cg_ms, 3),
+            "solver": f"flexible CG, window {window}, network every {period} steps",
+            "network": "U-Net 6 levels, 32..256 channels, bf16 MFMA, "
+                       f"{st['pairs']} operator-made pairs, {st['steps']} Adam steps x batch {st['batch']}",
+            "train_s": round(st["train_s"], 1), "network_apply_ms": round(net_ms, 3),
+            "operator_apply_ms": round(op_ms, 3),
+            "rel_residual": {"cg": cg["rel_residual"], "learned": ln["rel_residual"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction (learned vs CG) leg")
     ap.add_argument("--n-src", type=int, default=1440)
     ap.add_argument("--n-bins", type=int, default=3072)
     ap.add_argument("--grid", type=int, default=2048)
@@ -207,10 +282,13 @@ def main():
         "basis_evals_per_s": round(2 * nnz / (ms_per_step / 1e3), 1),
         "rays_per_s": round(M / (ms_per_step / 1e3), 1),
     }
+    plan.close()
+    del sino, back
+    if not args.no_recon:
+        result["recon"] = recon_leg(lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(spec, coeffs, n, M)
-    plan.close()
     print(json.dumps(result), flush=True)
 
 

@@ -157,9 +157,11 @@ typedef struct {
  *   over the last m directions, x += alpha p_k, r -= alpha M p_k,
  *   alpha = <r_k, p_k> / <p_k, M p_k>.  m = 1 is the Polak-Ribiere form
  *   beta_k = <z_k, r_k - r_{k-1}> / <z_{k-1}, r_{k-1}> (equal in exact
- *   arithmetic).  A network step is accepted only if the residual it
- *   produces, r - alpha M p with the exact operator, is smaller in norm than
- *   r; otherwise the step is recomputed with z_k = r_k (a CG step).
+ *   arithmetic).  The network proposes z_k on every `period`-th step (k = 0,
+ *   period, 2 period, ...; period >= 1), the other steps take z_k = r_k.  A
+ *   network step is accepted only if the residual it produces,
+ *   r - alpha M p with the exact operator, is smaller in norm than r;
+ *   otherwise the step is recomputed with z_k = r_k (a CG step).
  * Both stop on the updated residual and then confirm with b - M x computed
  * explicitly; if that check fails they continue from the true residual.
  * history (host, may be NULL) receives the relative residual after each
@@ -167,8 +169,8 @@ typedef struct {
  * synchronises with `stream` once per step.  Errors: EPLAN, EINVAL, ESIZE
  * (network image size differs from the plan's grid). */
 xrt_status xrt_solve(const xrt_plan* plan, float lambda, const float* b, float* x, float tol, int32_t maxit,
-                     xrt_unet* net, int32_t window, xrt_solve_info* info, double* history, int32_t history_cap,
-                     void* stream);
+                     xrt_unet* net, int32_t window, int32_t period, xrt_solve_info* info, double* history,
+                     int32_t history_cap, void* stream);
 
 #ifdef __cplusplus
 }

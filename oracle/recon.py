@@ -324,3 +324,27 @@ def adam_step(param, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def precond_loss_normal(flat, r, levels, base, n, line_cs, lam, gain=1.0, nx=None, ny=None):
+    """Residual-space training loss for the normal equations and its gradient.
+
+    loss = mean_b ||M N(r_b) - r_b||^2 / ||r_b||^2, M = H^T H + lam L^T L (the
+    oracle's transform).  With d_b = M z_b - r_b and z_b = N(r_b), the
+    gradient w.r.t. z_b is 2 M d_b / (B ||r_b||^2) (M is symmetric), and
+    z_b = gain rms(r_b) UNet(r_b / rms(r_b)) carries it to the network output.
+    """
+    r = np.asarray(r, dtype=np.float64)
+    B = r.shape[0]
+    rms = np.sqrt(np.mean(r * r, axis=(1, 2)))
+    y, cache = unet_forward(flat, r / rms[:, None, None], levels, base)
+    z = gain * y * rms[:, None, None]
+    gy = np.zeros_like(y)
+    loss = 0.0
+    for b in range(B):
+        d = normal_apply(n, z[b], line_cs, lam) - r[b]
+        rr = float(np.sum(r[b] * r[b]))
+        loss += float(np.sum(d * d)) / rr / B
+        gz = 2.0 * normal_apply(n, d, line_cs, lam) / (B * rr)
+        gy[b] = gz * gain * rms[b]
+    return loss, unet_backward(flat, cache, gy, levels, base)

@@ -108,7 +108,7 @@ def load() -> ctypes.CDLL:
     lib.xrt_conv3x3_forward.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.xrt_conv3x3_grad_input.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
     lib.xrt_conv3x3_grad_weight.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
-    lib.xrt_solve.argtypes = [vp, f32, vp, vp, f32, i32, vp, i32, ctypes.POINTER(XrtSolveInfo),
+    lib.xrt_solve.argtypes = [vp, f32, vp, vp, f32, i32, vp, i32, i32, ctypes.POINTER(XrtSolveInfo),
                               ctypes.POINTER(ctypes.c_double), i32, vp]
     for name in ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
                  "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_reg_apply",
@@ -266,9 +266,10 @@ def xrt_conv3x3_grad_weight(x, gy, B, H, W, cin, cout, gw, stream) -> int:
     return load().xrt_conv3x3_grad_weight(x, gy, int(B), int(H), int(W), int(cin), int(cout), gw, stream)
 
 
-def xrt_solve(plan, lam, b, x, tol, maxit, net, window, history_cap, stream):
+def xrt_solve(plan, lam, b, x, tol, maxit, net, window, period, history_cap, stream):
     info = XrtSolveInfo()
     hist = (ctypes.c_double * max(1, int(history_cap)))()
-    st = load().xrt_solve(plan, float(lam), b, x, float(tol), int(maxit), net, int(window), ctypes.byref(info),
+    st = load().xrt_solve(plan, float(lam), b, x, float(tol), int(maxit), net, int(window), int(period),
+                          ctypes.byref(info),
                           hist if history_cap > 0 else None, int(history_cap), stream)
     return st, info, [hist[i] for i in range(min(int(history_cap), info.iterations))]

@@ -57,6 +57,8 @@ struct xrt_unet {
     Buf gdd[8], gdh[8], gcat[8], guc[8], gebot, geh[8], gin[8];
     float *scale, *tn, *y, *gy, *lpart, *loss_tmp, *part;
     double* ipart;   // per-image reduction partials
+    float* cws;      // split-K partial sums of the 3x3 convolutions
+    int64_t cws_n;
     int64_t part_n;
     std::vector<void*> allocs;
 };
@@ -98,8 +100,8 @@ View genc_w(xrt_unet* n, int l) { return l == n->L - 1 ? n->gebot.v() : n->gcat[
 // output of decoder level l (l == L-1: the bottleneck)
 CView dec_out(const xrt_unet* n, int l) { return l == n->L - 1 ? n->ebot.cv() : n->dd[l].cv(); }
 
-hipError_t conv(CView x, const uint16_t* w, View y, CView mask, int B, int H, int W, int cin, int cout, bool relu,
-                hipStream_t s)
+hipError_t conv(xrt_unet* n, CView x, const uint16_t* w, View y, CView mask, int B, int H, int W, int cin, int cout,
+                bool relu, hipStream_t s)
 {
     xrl::ConvArgs a;
     a.x = x;
@@ -113,7 +115,7 @@ hipError_t conv(CView x, const uint16_t* w, View y, CView mask, int B, int H, in
     a.cin = cin;
     a.cout = cout;
     a.relu = relu ? 1 : 0;
-    return xrl::conv3x3(a, false, s);
+    return xrl::conv3x3(a, false, n->cws, n->cws_n, s);
 }
 
 hipError_t wgrad(xrt_unet* n, int k, CView x, CView g, int B, int H, int W, hipStream_t s)
@@ -166,18 +168,18 @@ hipError_t forward(xrt_unet* n, const float* r, const float* e, int B, hipStream
             XL_RUN(xrl::conv_in(r, n->scale, WF(n, enc_a(n, 0)), n->eh[0].v(), c, B, H, W, n->relu, s));
         } else {
             XL_RUN(xrl::avgpool2(enc_out(n, l - 1), n->in[l].v(), n->ch[l - 1], B, H * 2, W * 2, s));
-            XL_RUN(conv(n->in[l].cv(), WF(n, enc_a(n, l)), n->eh[l].v(), none, B, H, W, n->ch[l - 1], c, n->relu, s));
+            XL_RUN(conv(n, n->in[l].cv(), WF(n, enc_a(n, l)), n->eh[l].v(), none, B, H, W, n->ch[l - 1], c, n->relu, s));
         }
-        XL_RUN(conv(n->eh[l].cv(), WF(n, enc_b(n, l)), enc_out_w(n, l), none, B, H, W, c, c, n->relu, s));
+        XL_RUN(conv(n, n->eh[l].cv(), WF(n, enc_b(n, l)), enc_out_w(n, l), none, B, H, W, c, c, n->relu, s));
     }
     // decoder
     for (int l = L - 2; l >= 0; --l) {
         const int H = n->H >> l, W = n->W >> l, c = n->ch[l];
-        XL_RUN(conv(dec_out(n, l + 1), WF(n, dec_up(n, l)), n->uc[l].v(), none, B, H / 2, W / 2, n->ch[l + 1], c,
+        XL_RUN(conv(n, dec_out(n, l + 1), WF(n, dec_up(n, l)), n->uc[l].v(), none, B, H / 2, W / 2, n->ch[l + 1], c,
                     n->relu, s));
         XL_RUN(xrl::upsample2(n->uc[l].cv(), n->cat[l].v(c), c, B, H, W, s));
-        XL_RUN(conv(n->cat[l].cv(), WF(n, dec_a(n, l)), n->dh[l].v(), none, B, H, W, 2 * c, c, n->relu, s));
-        XL_RUN(conv(n->dh[l].cv(), WF(n, dec_b(n, l)), n->dd[l].v(), none, B, H, W, c, c, n->relu, s));
+        XL_RUN(conv(n, n->cat[l].cv(), WF(n, dec_a(n, l)), n->dh[l].v(), none, B, H, W, 2 * c, c, n->relu, s));
+        XL_RUN(conv(n, n->dh[l].cv(), WF(n, dec_b(n, l)), n->dd[l].v(), none, B, H, W, c, c, n->relu, s));
     }
     XL_RUN(xrl::conv_out(n->dd[0].cv(), WF(n, out_layer(n)), n->ch[0], n->y, (int)(B * npix), s));
     return hipSuccess;
@@ -203,25 +205,25 @@ hipError_t backward(xrt_unet* n, const float* r, int B, hipStream_t s)
     for (int l = 0; l <= L - 2; ++l) {
         const int H = n->H >> l, W = n->W >> l, c = n->ch[l];
         XL_RUN(wgrad(n, dec_b(n, l), n->dh[l].cv(), n->gdd[l].cv(), B, H, W, s));
-        XL_RUN(conv(n->gdd[l].cv(), WB(n, dec_b(n, l)), n->gdh[l].v(), MK(n->dh[l].cv()), B, H, W, c, c, false, s));
+        XL_RUN(conv(n, n->gdd[l].cv(), WB(n, dec_b(n, l)), n->gdh[l].v(), MK(n->dh[l].cv()), B, H, W, c, c, false, s));
         XL_RUN(wgrad(n, dec_a(n, l), n->cat[l].cv(), n->gdh[l].cv(), B, H, W, s));
-        XL_RUN(conv(n->gdh[l].cv(), WB(n, dec_a(n, l)), n->gcat[l].v(), MK(n->cat[l].cv()), B, H, W, c, 2 * c, false,
+        XL_RUN(conv(n, n->gdh[l].cv(), WB(n, dec_a(n, l)), n->gcat[l].v(), MK(n->cat[l].cv()), B, H, W, c, 2 * c, false,
                     s));
         XL_RUN(xrl::upsample2_T(n->gcat[l].cv(c), n->guc[l].v(), c, B, H, W, s));
         XL_RUN(wgrad(n, dec_up(n, l), dec_out(n, l + 1), n->guc[l].cv(), B, H / 2, W / 2, s));
         const View tgt = (l + 1 == L - 1) ? n->gebot.v() : n->gdd[l + 1].v();
-        XL_RUN(conv(n->guc[l].cv(), WB(n, dec_up(n, l)), tgt, MK(dec_out(n, l + 1)), B, H / 2, W / 2, c, n->ch[l + 1],
+        XL_RUN(conv(n, n->guc[l].cv(), WB(n, dec_up(n, l)), tgt, MK(dec_out(n, l + 1)), B, H / 2, W / 2, c, n->ch[l + 1],
                     false, s));
     }
     // encoder, coarse to fine; genc(l) holds the masked gradient of encoder level l's output
     for (int l = L - 1; l >= 0; --l) {
         const int H = n->H >> l, W = n->W >> l, c = n->ch[l];
         XL_RUN(wgrad(n, enc_b(n, l), n->eh[l].cv(), genc(n, l), B, H, W, s));
-        XL_RUN(conv(genc(n, l), WB(n, enc_b(n, l)), n->geh[l].v(), MK(n->eh[l].cv()), B, H, W, c, c, false, s));
+        XL_RUN(conv(n, genc(n, l), WB(n, enc_b(n, l)), n->geh[l].v(), MK(n->eh[l].cv()), B, H, W, c, c, false, s));
         if (l > 0) {
             const int cp = n->ch[l - 1];
             XL_RUN(wgrad(n, enc_a(n, l), n->in[l].cv(), n->geh[l].cv(), B, H, W, s));
-            XL_RUN(conv(n->geh[l].cv(), WB(n, enc_a(n, l)), n->gin[l].v(), CView{nullptr, 0}, B, H, W, c, cp, false,
+            XL_RUN(conv(n, n->geh[l].cv(), WB(n, enc_a(n, l)), n->gin[l].v(), CView{nullptr, 0}, B, H, W, c, cp, false,
                         s));
             XL_RUN(xrl::avgpool2_T_add(n->gin[l].cv(), genc_w(n, l - 1), MK(enc_out(n, l - 1)), cp, B, 2 * H, 2 * W, s));
         } else {
@@ -356,6 +358,19 @@ xrt_status xrt_unet_create(int32_t levels, int32_t base, int32_t max_channels, i
         if (need > part_n) part_n = need;
     }
     n->part_n = part_n;
+    int64_t cws_n = 0;
+    for (size_t k = 0; k < n->layers.size(); ++k) {
+        const Layer& Ly = n->layers[k];
+        if (!(Ly.taps == 9 && Ly.cin % 32 == 0)) continue;
+        // the split depends on the batch actually passed (<= max_batch)
+        for (int lev = 0; lev < levels; ++lev)
+            for (int b = 1; b <= std::min(B, 64); ++b) {
+                const int H = height >> lev, W = width >> lev;
+                cws_n = std::max(cws_n, xrl::conv3x3_ws_floats(b, H, W, Ly.cin, Ly.cout));
+                cws_n = std::max(cws_n, xrl::conv3x3_ws_floats(b, H, W, Ly.cout, Ly.cin));
+            }
+    }
+    n->cws_n = cws_n;
 
     bool ok = true;
     auto alloc = [&](size_t bytes) -> void* {
@@ -411,6 +426,7 @@ xrt_status xrt_unet_create(int32_t levels, int32_t base, int32_t max_channels, i
     n->loss_tmp = (float*)alloc(sizeof(float));
     n->part = (float*)alloc(part_n * sizeof(float));
     n->ipart = (double*)alloc((size_t)xrl::image_parts() * 2 * B * sizeof(double));
+    n->cws = n->cws_n > 0 ? (float*)alloc(n->cws_n * sizeof(float)) : nullptr;
     if (!ok) {
         free_all(n);
         delete n;
@@ -607,7 +623,13 @@ xrt_status xrt_conv3x3_forward(const uint16_t* x, const uint16_t* w, int32_t B, 
     a.cin = cin;
     a.cout = cout;
     a.relu = relu ? 1 : 0;
-    XL_CHECK(xrl::conv3x3(a, true, (hipStream_t)stream), "conv3x3");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t wn = xrl::conv3x3_ws_floats(B, H, W, cin, cout);
+    float* ws = nullptr;
+    if (wn > 0) XL_CHECK(hipMallocAsync((void**)&ws, wn * sizeof(float), s), "hipMallocAsync");
+    hipError_t e = xrl::conv3x3(a, true, ws, wn, s);
+    if (ws) (void)hipFreeAsync(ws, s);
+    XL_CHECK(e, "conv3x3");
     return XRT_OK;
 }
 
@@ -633,8 +655,13 @@ xrt_status xrt_conv3x3_grad_input(const uint16_t* gy, const uint16_t* w, int32_t
     a.cin = cout;
     a.cout = cin;
     a.relu = 0;
-    XL_CHECK(xrl::conv3x3(a, true, s), "conv3x3");
+    const int64_t wn = xrl::conv3x3_ws_floats(B, H, W, cout, cin);
+    float* ws = nullptr;
+    if (wn > 0) XL_CHECK(hipMallocAsync((void**)&ws, wn * sizeof(float), s), "hipMallocAsync");
+    hipError_t e = xrl::conv3x3(a, true, ws, wn, s);
+    if (ws) (void)hipFreeAsync(ws, s);
     (void)hipFreeAsync(wflip, s);
+    XL_CHECK(e, "conv3x3");
     return XRT_OK;
 }
 
@@ -668,11 +695,11 @@ xrt_status xrt_conv3x3_grad_weight(const uint16_t* x, const uint16_t* gy, int32_
 enum { S_RR = 0, S_PQ, S_RP, S_RRN, S_BB, S_ZQ = 8, S_PQR = S_ZQ + xrl::kMaxVecs, S_N = S_PQR + xrl::kMaxVecs };
 
 xrt_status xrt_solve(const xrt_plan* plan, float lambda, const float* b, float* x, float tol, int32_t maxit,
-                     xrt_unet* net, int32_t window, xrt_solve_info* info, double* history, int32_t history_cap,
-                     void* stream)
+                     xrt_unet* net, int32_t window, int32_t period, xrt_solve_info* info, double* history,
+                     int32_t history_cap, void* stream)
 {
     if (!b || !x || !info || !(tol > 0.f) || maxit < 0) return XRT_EINVAL;
-    if (net && (window < 1 || window > xrl::kMaxVecs)) return XRT_EINVAL;
+    if (net && (window < 1 || window > xrl::kMaxVecs || period < 1)) return XRT_EINVAL;
     int64_t m = 0, crossing = 0;
     xrt_status st = xrt_plan_info(plan, &m, &crossing);
     if (st != XRT_OK) return st;
@@ -772,8 +799,9 @@ xrt_status xrt_solve(const xrt_plan* plan, float lambda, const float* b, float* 
                 XS(read_slots(), "sync");
                 rel = sqrt(host[S_RR]) / bn;
             } else {
-                // flexible CG: the new direction is M-orthogonalised against the last `win` ones
-                bool learned = true;
+                // flexible CG: the new direction is M-orthogonalised against the last `win` ones;
+                // the network proposes every `period`-th step, the others take z = r
+                bool learned = info->iterations % period == 0;
                 for (;;) {
                     const float* zz = r;
                     if (learned) {

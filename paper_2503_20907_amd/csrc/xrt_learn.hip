@@ -53,7 +53,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, n = l & 31, kg = l >> 5;
     const int ntw = (a.W + kTW - 1) / kTW;
     const int w0 = (blockIdx.x % ntw) * kTW, h0 = (blockIdx.x / ntw) * kTR;
-    const int b = blockIdx.y, co0 = blockIdx.z * COT;
+    const int ncb = a.cout / COT;
+    const int b = blockIdx.y, co0 = (blockIdx.z % ncb) * COT, kp = blockIdx.z / ncb;
+    const int nch = a.cin / 32;
+    const int c_lo = (int)((int64_t)kp * nch / a.ksplit), c_hi = (int)((int64_t)(kp + 1) * nch / a.ksplit);
     f32x16 acc[COT / 32][2];
 #pragma unroll
     for (int i = 0; i < COT / 32; ++i)
@@ -61,7 +64,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
         for (int j = 0; j < 2; ++j)
             for (int k = 0; k < 16; ++k) acc[i][j][k] = 0.f;
 
-    for (int ci0 = 0; ci0 < a.cin; ci0 += 32) {
+    for (int ci0 = 32 * c_lo; ci0 < 32 * c_hi; ci0 += 32) {
         __syncthreads();
         for (int v = tid; v < (kTR + 2) * kXW * 4; v += 256) {
             const int q = v & 3, pix = v >> 2;
@@ -107,6 +110,19 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
         const int px = w0 + pb * 32 + n;
         if (px >= a.W) continue;
         const size_t pix = (size_t)(b * a.H + h) * a.W + px;
+        if (a.ksplit > 1) {
+            // raw partial sums; the reduction applies the epilogue
+            float* kq = a.kpart + ((size_t)kp * a.B * a.H * a.W + pix) * a.cout;
+#pragma unroll
+            for (int cb = 0; cb < COT / 32; ++cb)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int co = co0 + cb * 32 + 8 * g + 4 * kg;
+                    *reinterpret_cast<float4*>(kq + co) = make_float4(acc[cb][pb][4 * g], acc[cb][pb][4 * g + 1],
+                                                                      acc[cb][pb][4 * g + 2], acc[cb][pb][4 * g + 3]);
+                }
+            continue;
+        }
 #pragma unroll
         for (int cb = 0; cb < COT / 32; ++cb) {
 #pragma unroll
@@ -134,6 +150,42 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
                 }
             }
         }
+    }
+}
+
+// Sum of the split-K partials, then the convolution's epilogue (ReLU, mask,
+// store).  Thread per (pixel, 4 output channels).
+__global__ void k_conv_reduce(ConvArgs a, int f32out)
+{
+    const int64_t npix = (int64_t)a.B * a.H * a.W;
+    const int nq = a.cout / 4;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= npix * nq) return;
+    const int co = 4 * (int)(idx % nq);
+    const int64_t pix = idx / nq;
+    float4 v = *reinterpret_cast<const float4*>(a.kpart + pix * a.cout + co);
+    for (int k = 1; k < a.ksplit; ++k) {
+        const float4 u = *reinterpret_cast<const float4*>(a.kpart + ((int64_t)k * npix + pix) * a.cout + co);
+        v.x += u.x;
+        v.y += u.y;
+        v.z += u.z;
+        v.w += u.w;
+    }
+    float w4[4] = {v.x, v.y, v.z, v.w};
+    if (a.relu)
+        for (int j = 0; j < 4; ++j) w4[j] = fmaxf(w4[j], 0.f);
+    if (a.mask.p) {
+        const u32x2 m = *reinterpret_cast<const u32x2*>(a.mask.p + pix * a.mask.pitch + co);
+        if (!bf_pos(m[0] & 0xFFFFu)) w4[0] = 0.f;
+        if (!bf_pos(m[0] >> 16)) w4[1] = 0.f;
+        if (!bf_pos(m[1] & 0xFFFFu)) w4[2] = 0.f;
+        if (!bf_pos(m[1] >> 16)) w4[3] = 0.f;
+    }
+    if (f32out) {
+        *reinterpret_cast<float4*>(static_cast<float*>(a.y) + pix * a.ypitch + co) = make_float4(w4[0], w4[1], w4[2], w4[3]);
+    } else {
+        *reinterpret_cast<u32x2*>(static_cast<uint16_t*>(a.y) + pix * a.ypitch + co) =
+            u32x2{pack2(w4[0], w4[1]), pack2(w4[2], w4[3])};
     }
 }
 
@@ -737,18 +789,49 @@ __global__ void k_orth(int64_t n, const double* slots, int a, int b, int k, cons
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t conv3x3(const ConvArgs& a, bool f32_out, hipStream_t s)
+// tiles x images x output-channel blocks of the unsplit launch, and the split
+// that brings it to about 512 workgroups (at most one chunk of 32 input
+// channels per split)
+static void conv_shape(int B, int H, int W, int cin, int cout, bool* wide, int* ksplit)
 {
-    if (a.cin % 32 || a.cout % 32 || a.B <= 0 || a.H <= 0 || a.W <= 0 || a.B > 65535) return hipErrorInvalidValue;
+    const int64_t ntiles = (int64_t)((W + kTW - 1) / kTW) * ((H + kTR - 1) / kTR);
+    *wide = cout % 64 == 0 && ntiles * B * (cout / 64) >= 512;
+    const int64_t wgs = ntiles * B * (cout / (*wide ? 64 : 32));
+    int k = 1;
+    while (wgs * k * 2 <= 512 && k * 2 <= cin / 32) k *= 2;
+    *ksplit = k;
+}
+
+int64_t conv3x3_ws_floats(int B, int H, int W, int cin, int cout)
+{
+    bool wide;
+    int k;
+    conv_shape(B, H, W, cin, cout, &wide, &k);
+    return k > 1 ? (int64_t)k * B * H * W * cout : 0;
+}
+
+hipError_t conv3x3(const ConvArgs& a0, bool f32_out, float* ws, int64_t ws_floats, hipStream_t s)
+{
+    if (a0.cin % 32 || a0.cout % 32 || a0.B <= 0 || a0.H <= 0 || a0.W <= 0 || a0.B > 65535) return hipErrorInvalidValue;
+    ConvArgs a = a0;
     const int ntiles = ((a.W + kTW - 1) / kTW) * ((a.H + kTR - 1) / kTR);
-    const bool wide = a.cout % 64 == 0 && (int64_t)ntiles * a.B * (a.cout / 64) >= 512;
-    const dim3 grid(ntiles, a.B, a.cout / (wide ? 64 : 32));
+    bool wide;
+    int k;
+    conv_shape(a.B, a.H, a.W, a.cin, a.cout, &wide, &k);
+    if (k > 1 && (!ws || (int64_t)k * a.B * a.H * a.W * a.cout > ws_floats)) k = 1;
+    a.ksplit = k;
+    a.kpart = k > 1 ? ws : nullptr;
+    const dim3 grid(ntiles, a.B, (a.cout / (wide ? 64 : 32)) * k);
     if (wide) {
         if (f32_out) hipLaunchKernelGGL((k_conv3x3<64, true>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_conv3x3<64, false>), grid, dim3(256), 0, s, a);
     } else {
         if (f32_out) hipLaunchKernelGGL((k_conv3x3<32, true>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_conv3x3<32, false>), grid, dim3(256), 0, s, a);
+    }
+    if (k > 1) {
+        const int64_t n = (int64_t)a.B * a.H * a.W * (a.cout / 4);
+        hipLaunchKernelGGL(k_conv_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, f32_out ? 1 : 0);
     }
     return hipGetLastError();
 }

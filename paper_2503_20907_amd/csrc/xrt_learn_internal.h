@@ -34,6 +34,11 @@ struct ConvArgs {
     CView mask;          // p == nullptr: none
     int B, H, W, cin, cout;
     int relu;
+    // split of the input-channel reduction over workgroups (set by conv3x3):
+    // ksplit > 1 writes fp32 partial sums kpart[k][pixel][cout], then a
+    // reduction applies the activation and mask
+    int ksplit;
+    float* kpart;
 };
 
 // Weight gradient of the convolution above: per region of pixels, partial
@@ -45,7 +50,11 @@ struct WgradArgs {
     int rows;            // image rows per region (even)
 };
 
-hipError_t conv3x3(const ConvArgs& a, bool f32_out, hipStream_t s);
+// `ws` (may be null: no split) is a workspace of ws_floats floats for the
+// split-K partial sums
+hipError_t conv3x3(const ConvArgs& a, bool f32_out, float* ws, int64_t ws_floats, hipStream_t s);
+// the largest workspace conv3x3 can use for this shape (0: it never splits)
+int64_t conv3x3_ws_floats(int B, int H, int W, int cin, int cout);
 hipError_t conv3x3_wgrad(const WgradArgs& a, int* n_regions, hipStream_t s);
 int wgrad_rows(int B, int H, int W, int cin, int cout);
 int64_t wgrad_regions(int B, int H, int W, int rows);

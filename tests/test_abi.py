@@ -135,9 +135,9 @@ def test_learn_entry_points_reject_bad_arguments():
     assert lib.xrt_reg_apply(1, 0, 8, ctypes.c_float(1.0), 1, None) == L.XRT_EINVAL
     assert lib.xrt_normal_apply(None, ctypes.c_float(1.0), 1, 1, None, None) == L.XRT_EPLAN
     info = L.XrtSolveInfo()
-    assert lib.xrt_solve(None, ctypes.c_float(1.0), 1, 1, ctypes.c_float(1e-3), 10, None, 1,
+    assert lib.xrt_solve(None, ctypes.c_float(1.0), 1, 1, ctypes.c_float(1e-3), 10, None, 1, 1,
                          ctypes.byref(info), None, 0, None) == L.XRT_EPLAN
-    assert lib.xrt_solve(1, ctypes.c_float(1.0), 1, 1, ctypes.c_float(0.0), 10, None, 1,
+    assert lib.xrt_solve(1, ctypes.c_float(1.0), 1, 1, ctypes.c_float(0.0), 10, None, 1, 1,
                          ctypes.byref(info), None, 0, None) == L.XRT_EINVAL
     # convolutions need channel counts that are multiples of 32
     assert lib.xrt_conv3x3_forward(1, 1, 1, 8, 8, 16, 32, 0, 1, None) == L.XRT_EINVAL

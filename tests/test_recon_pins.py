@@ -189,3 +189,29 @@ def test_cg_solves_the_dense_system():
     xd = np.linalg.solve(H.T @ H + lam * Lt, b.ravel())
     assert np.allclose(x.ravel(), xd, rtol=1e-8, atol=1e-8)
     assert hist[-1] <= 1e-12 and it <= N * N + 20
+
+
+def test_residual_loss_gradient_matches_central_differences():
+    # the residual-space loss chains the network with the normal operator
+    n, N, lam, levels, base = 1, 8, 0.05, 2, 2
+    rng = _rng(15)
+    th = rng.uniform(0, math.pi, 10).astype(np.float32)
+    y = rng.uniform(-4, 4, 10).astype(np.float32)
+    lc = oracle.lines_from_theta_y(th, y)
+    shapes = [s for _, s in R.unet_layout(levels, base)]
+    nprm = sum(int(np.prod(s)) for s in shapes)
+    flat = rng.normal(size=nprm) * 0.5
+    r = rng.normal(size=(2, N, N))
+    loss, g = R.precond_loss_normal(flat, r, levels, base, n, lc, lam, gain=0.3)
+    h = 1e-6
+    for k in rng.choice(nprm, 25, replace=False):
+        fp, fm = flat.copy(), flat.copy()
+        fp[k] += h
+        fm[k] -= h
+        fd = (R.precond_loss_normal(fp, r, levels, base, n, lc, lam, 0.3)[0]
+              - R.precond_loss_normal(fm, r, levels, base, n, lc, lam, 0.3)[0]) / (2 * h)
+        assert abs(g[k] - fd) < 1e-6 * max(1.0, abs(fd)), (k, g[k], fd)
+    # the loss is the relative residual of one step x += N(r)
+    z = R.precondition(flat, r, levels, base, gain=0.3)
+    ref = np.mean([np.sum((R.normal_apply(n, z[b], lc, lam) - r[b]) ** 2) / np.sum(r[b] ** 2) for b in range(2)])
+    assert abs(loss - ref) < 1e-12 * ref
