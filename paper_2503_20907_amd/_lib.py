@@ -25,14 +25,23 @@ XRT_EPLAN = -6
 XRT_LINES_THETA_Y = 0
 XRT_LINES_ENDPOINTS = 1
 
-# every symbol declared in include/xrt.h and include/xrt_learn.h
-EXPORTS = ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
-           "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_plan_destroy",
-           "xrt_status_string", "xrt_last_error", "xrt_version",
-           "xrt_reg_apply", "xrt_normal_apply", "xrt_unet_create", "xrt_unet_destroy",
-           "xrt_unet_num_params", "xrt_unet_set_params", "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_get_params", "xrt_unet_apply",
-           "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
-           "xrt_unet_train_step_normal", "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve")
+# every symbol declared in include/*.h
+EXPORTS = (
+    # xrt.h
+    "xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward", "xrt_plan_adjoint",
+    "xrt_plan_info", "xrt_plan_nnz", "xrt_plan_destroy", "xrt_status_string", "xrt_last_error",
+    "xrt_version",
+    # xrt_learn.h
+    "xrt_reg_apply", "xrt_normal_apply", "xrt_unet_create", "xrt_unet_destroy", "xrt_unet_num_params",
+    "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_set_gain", "xrt_unet_get_gain",
+    "xrt_unet_set_relu", "xrt_unet_apply", "xrt_unet_loss_grad", "xrt_unet_train_step",
+    "xrt_unet_loss_grad_normal", "xrt_unet_train_step_normal", "xrt_conv3x3_forward",
+    "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve",
+    # xrt_batch.h
+    "xrt_batch_create", "xrt_batch_destroy", "xrt_batch_buffers", "xrt_batch_info", "xrt_batch_forward",
+    "xrt_batch_adjoint", "xrt_batch_run", "xrt_batch_get_config", "xrt_batch_set_config",
+    "xrt_batch_autotune",
+)
 
 
 class XrtGrid(ctypes.Structure):
@@ -51,6 +60,15 @@ class XrtSolveInfo(ctypes.Structure):
                 ("learned_accepted", ctypes.c_int32), ("learned_rejected", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double)]
+
+
+class XrtProblem(ctypes.Structure):
+    _fields_ = [("grid", XrtGrid), ("degree", ctypes.c_int32), ("lines", XrtLines)]
+
+
+class XrtBatchConfig(ctypes.Structure):
+    _fields_ = [("fwd_blocks_per_cu", ctypes.c_int32), ("lines_per_item", ctypes.c_int32),
+                ("adj_blocks_per_cu", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class XrtError(RuntimeError):
@@ -110,6 +128,22 @@ def load() -> ctypes.CDLL:
     lib.xrt_conv3x3_grad_weight.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
     lib.xrt_solve.argtypes = [vp, f32, vp, vp, f32, i32, vp, i32, i32, ctypes.POINTER(XrtSolveInfo),
                               ctypes.POINTER(ctypes.c_double), i32, vp]
+    fpp = ctypes.POINTER(ctypes.c_void_p)
+    lib.xrt_batch_create.argtypes = [ctypes.POINTER(XrtProblem), i32, vp, ctypes.POINTER(vp)]
+    lib.xrt_batch_destroy.argtypes = [vp]
+    lib.xrt_batch_destroy.restype = None
+    lib.xrt_batch_buffers.argtypes = [vp, i32, fpp, fpp, fpp]
+    lib.xrt_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.xrt_batch_forward.argtypes = [vp, vp]
+    lib.xrt_batch_adjoint.argtypes = [vp, vp]
+    lib.xrt_batch_run.argtypes = [vp, i32, vp]
+    lib.xrt_batch_get_config.argtypes = [vp, ctypes.POINTER(XrtBatchConfig)]
+    lib.xrt_batch_set_config.argtypes = [vp, ctypes.POINTER(XrtBatchConfig)]
+    lib.xrt_batch_autotune.argtypes = [vp, i32, ctypes.POINTER(XrtBatchConfig), vp]
+    for name in ("xrt_batch_create", "xrt_batch_buffers", "xrt_batch_info", "xrt_batch_forward",
+                 "xrt_batch_adjoint", "xrt_batch_run", "xrt_batch_get_config", "xrt_batch_set_config",
+                 "xrt_batch_autotune"):
+        getattr(lib, name).restype = i32
     for name in ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
                  "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_reg_apply",
                  "xrt_normal_apply", "xrt_unet_create", "xrt_unet_num_params",
@@ -273,3 +307,55 @@ def xrt_solve(plan, lam, b, x, tol, maxit, net, window, period, history_cap, str
                           ctypes.byref(info),
                           hist if history_cap > 0 else None, int(history_cap), stream)
     return st, info, [hist[i] for i in range(min(int(history_cap), info.iterations))]
+
+
+# ---------------------------------------------------------- include/xrt_batch.h
+def xrt_batch_create(problems, stream):
+    arr = (XrtProblem * len(problems))(*problems)
+    out = ctypes.c_void_p()
+    st = load().xrt_batch_create(arr, len(problems), stream, ctypes.byref(out))
+    return st, out.value
+
+
+def xrt_batch_destroy(b) -> None:
+    load().xrt_batch_destroy(b)
+
+
+def xrt_batch_buffers(b, p):
+    c, s, k = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    st = load().xrt_batch_buffers(b, int(p), ctypes.byref(c), ctypes.byref(s), ctypes.byref(k))
+    return st, c.value, s.value, k.value
+
+
+def xrt_batch_info(b):
+    n, f, a = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    st = load().xrt_batch_info(b, ctypes.byref(n), ctypes.byref(f), ctypes.byref(a))
+    return st, n.value, f.value, a.value
+
+
+def xrt_batch_forward(b, stream) -> int:
+    return load().xrt_batch_forward(b, stream)
+
+
+def xrt_batch_adjoint(b, stream) -> int:
+    return load().xrt_batch_adjoint(b, stream)
+
+
+def xrt_batch_run(b, use_graph, stream) -> int:
+    return load().xrt_batch_run(b, int(use_graph), stream)
+
+
+def xrt_batch_get_config(b):
+    c = XrtBatchConfig()
+    st = load().xrt_batch_get_config(b, ctypes.byref(c))
+    return st, c
+
+
+def xrt_batch_set_config(b, cfg: XrtBatchConfig) -> int:
+    return load().xrt_batch_set_config(b, ctypes.byref(cfg))
+
+
+def xrt_batch_autotune(b, reps, stream):
+    c = XrtBatchConfig()
+    st = load().xrt_batch_autotune(b, int(reps), ctypes.byref(c), stream)
+    return st, c

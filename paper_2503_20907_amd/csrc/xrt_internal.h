@@ -95,6 +95,21 @@ hipError_t launch_header(PlanHeader* hdr, const uint32_t* off, int64_t vert_end,
 hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, hipStream_t s);
 hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s);
 hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s);
+
+// batches of plans (one persistent launch per direction; see xrt_batch.cpp)
+size_t batch_prob_size();
+// strips of the forward schedule of a plan (per-strip partial sums: strips x lines floats)
+int batch_strips(const xrt_plan* p);
+// writes the per-problem launch record (batch_prob_size() bytes) to dst (host memory)
+void batch_fill(const xrt_plan* p, float* sino, float* back, float* spart, void* dst);
+hipError_t launch_batch_fwd_reduce(const void* probs, int p, int64_t m, hipStream_t s);
+hipError_t launch_layouts(const xrt_plan* p, const float* coeffs, hipStream_t s);
+hipError_t launch_sort_sino(const xrt_plan* p, const float* sino, hipStream_t s);
+hipError_t launch_reset_counters(unsigned int* c, int n, hipStream_t s);
+hipError_t launch_batch_forward(const void* probs, const int2* items, int nitems, unsigned int* counter,
+                                int lines_per_item, int grid, hipStream_t s);
+hipError_t launch_batch_adjoint(const void* probs, const int2* items, int nitems, unsigned int* counter, int grid,
+                                hipStream_t s);
 // Knot-transition table of degree n (host, FP64-built, rounded to float):
 // kTabPerUnit*(n+1)/2 cubic intervals plus one zero interval, 4 floats each.
 const float* etable_host(int n, int* n_entries);

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "xrt_internal.h"
 
@@ -578,6 +579,34 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     else if (ja <= jb) A.part[k] += (double)acc;
 }
 
+// Line k over all its rows (no strips), scaled and written to the caller's
+// order: the per-line work of the batched forward.  Lanes of a wave that
+// call it together share the knot-slot count (wave_slots).
+template <int N, bool VERT>
+__device__ inline void fwd_line_full(const FwdArgs& A, int64_t k, const float4* __restrict__ s_tab)
+{
+    const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
+    const double H = 0.5 * (N + 1);
+    const double xc = A.xc[k], kap = A.kap[k];
+    const double x0 = xc - kap * (0.5 * (nmaj - 1));
+    int ja, jb;
+    row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &ja, &jb);
+    const LineConst lc = line_const<N>(kap);
+    const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
+    float acc = 0.f;
+    if (ja <= jb) {
+        const int pitch = VERT ? A.pitch_v : A.pitch_h;
+        const float* __restrict__ C = VERT ? A.cv : A.ch;
+        const float* __restrict__ D = VERT ? A.dv : A.dh;
+        const double q0 = x0 + kap * (double)ja + H;
+        if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+    }
+    A.sino[A.idx[k]] = (float)((double)acc * A.h * sqrt(1.0 + kap * kap) / (double)tap_scale<N>());
+}
+
 // sino[idx[k]] = (sum over strips of part[s][k]) * h / max(|cos|,|sin|);
 // lines that miss the grid get 0.
 template <int N>
@@ -757,23 +786,31 @@ __device__ inline float block_max(float v, float* red)
 #define XRT_ADJ_WAVES 4
 #endif
 #define XRT_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(XRT_ADJ_WAVES, XRT_ADJ_WAVES)))
+// LDS of one adjoint workgroup
+struct AdjShared {
+    int a[kAccWords];
+    int k[kAccWords];
+    float4 tab[kTabMax];
+    uint32_t start[kSlopeBins];
+    uint32_t pre[kSlopeBins + 1];
+    uint32_t scan[kBlock];
+    float red[4];
+};
+
+// One pixel tile of the adjoint (both orientations); `kpart` selects this
+// workgroup's share of the candidate chunks when A.split > 1.  The table
+// must already be in sh.tab.
 template <int N>
-__global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
+__device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, AdjShared& sh)
 {
-    __shared__ int s_a[kAccWords];
-    __shared__ int s_k[kAccWords];
-    __shared__ float4 s_tab[kTabMax];
-    __shared__ uint32_t s_start[kSlopeBins];
-    __shared__ uint32_t s_pre[kSlopeBins + 1];
-    __shared__ uint32_t s_scan[kBlock];
-    __shared__ float s_red[4];
-
+    int* s_a = sh.a;
+    int* s_k = sh.k;
+    const float4* s_tab = sh.tab;
+    uint32_t* s_start = sh.start;
+    uint32_t* s_pre = sh.pre;
+    uint32_t* s_scan = sh.scan;
+    float* s_red = sh.red;
     const int tid = threadIdx.x;
-    const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
-    for (int e = tid; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
-
-    const int tile = xcd_logical(blockIdx.x, A.ntiles_pad);
-    if (tile >= A.ntiles) return;  // uniform per block
     const int ti = tile % A.tiles_i, tj = tile / A.tiles_i;
     const int i0 = ti * kTileI, j0 = tj * kTileJ;
     // a row whose crossing X lies outside (min0 - (n+1), min0 + TN + n) adds
@@ -834,7 +871,7 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
         __syncthreads();
         const uint32_t total = s_pre[kSlopeBins];
 
-        for (uint32_t base = blockIdx.y * 2u * kBlock; base < total; base += (uint32_t)A.split * 2u * kBlock) {
+        for (uint32_t base = (uint32_t)kpart * 2u * kBlock; base < total; base += (uint32_t)A.split * 2u * kBlock) {
             uint32_t kk[2] = {0, 0};
             float svv[2] = {0.f, 0.f};
 #pragma unroll
@@ -890,10 +927,21 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
         const int pj = p / kTileI, pi = p % kTileI;
         const int i = i0 + pi, j = j0 + pj;
         if (i < A.nx && j < A.ny) {
-            if (A.split > 1) A.part[((int64_t)blockIdx.y * A.ny + j) * A.nx + i] = o[e];
+            if (A.split > 1) A.part[((int64_t)kpart * A.ny + j) * A.nx + i] = o[e];
             else A.out[(int64_t)j * A.nx + i] = o[e];
         }
     }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
+{
+    __shared__ AdjShared sh;
+    const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
+    for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
+    const int tile = xcd_logical(blockIdx.x, A.ntiles_pad);
+    if (tile >= A.ntiles) return;  // uniform per block
+    adj_tile<N>(A, tile, (int)blockIdx.y, sh);
 }
 
 // out = sum over the split workgroups' partial images, in a fixed order
@@ -905,6 +953,158 @@ __global__ void __launch_bounds__(kBlock) k_adj_reduce(const float* part, int sp
     for (int g = 1; g < split; ++g) v += part[(int64_t)g * npix + k];
     out[k] = v;
 }
+
+// ---------------------------------------------------------------- batch
+struct BatchProb {
+    FwdArgs f;      // forward of this problem (sino = its sinogram buffer)
+    AdjArgs a;      // adjoint of this problem (split 1, out = its image buffer)
+    int degree;
+    int nstrip;     // strips of kStrip rows (the larger of the two orientations)
+    int64_t m_vert, m_valid;
+    float* spart;   // [nstrip][m] per-strip line sums (unscaled)
+};
+struct BatchArgs {
+    const BatchProb* probs;
+    const int2* items;   // (problem, line block or tile)
+    int nitems;
+    unsigned int* counter;
+    int lines_per_item;  // forward: lines per item, a multiple of kBlock
+};
+
+// Many problems (each with its own plan) in one persistent launch per
+// direction.  Work items (problem, block of lines) for the forward and
+// (problem, tile) for the adjoint are listed largest problem first; every
+// workgroup takes the next item from one atomic counter until the list is
+// exhausted (the only atomic: the adjoint of an item is the gather of one
+// tile, written once).
+// Line k over the rows of strip `st` (unscaled sum into spart[st][k]).
+template <int N, bool VERT>
+__device__ inline void fwd_line_strip(const BatchProb& P, int64_t k, int st, const float4* __restrict__ s_tab)
+{
+    const FwdArgs& A = P.f;
+    const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
+    const double H = 0.5 * (N + 1);
+    const double xc = A.xc[k], kap = A.kap[k];
+    const double x0 = xc - kap * (0.5 * (nmaj - 1));
+    int jlo, jhi;
+    row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+    const int ja = max(jlo, st * kStrip), jb = min(jhi, st * kStrip + kStrip - 1);
+    const LineConst lc = line_const<N>(kap);
+    const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
+    float acc = 0.f;
+    if (ja <= jb) {
+        const int pitch = VERT ? A.pitch_v : A.pitch_h;
+        const float* __restrict__ C = VERT ? A.cv : A.ch;
+        const float* __restrict__ D = VERT ? A.dv : A.dh;
+        const double q0 = x0 + kap * (double)ja + H;
+        if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+    }
+    P.spart[(int64_t)st * A.m + k] = acc;
+}
+
+template <int N>
+__device__ inline void fwd_block_any(const BatchProb& P, int64_t k0, int st, const float4* __restrict__ s_tab)
+{
+    const int64_t k = k0 + threadIdx.x;
+    if (k < P.m_vert) fwd_line_strip<N, true>(P, k, st, s_tab);
+    else if (k < P.m_valid) fwd_line_strip<N, false>(P, k, st, s_tab);
+}
+
+__device__ inline int next_item(unsigned int* counter, int* s_item)
+{
+    __syncthreads();   // everyone is done with the previous item (and with *s_item)
+    if (threadIdx.x == 0) *s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    return *s_item;
+}
+
+// items (problem, strip * blocks + block): the items of one problem are
+// listed strip by strip, so the workgroups in flight share one strip of its
+// layouts (as in the single-problem schedule)
+__global__ void __launch_bounds__(kBlock) k_batch_forward(BatchArgs B)
+{
+    __shared__ float4 s_tab[kTabMax];
+    __shared__ int s_item;
+    int cur = -1;
+    for (;;) {
+        const int it = next_item(B.counter, &s_item);
+        if (it >= B.nitems) break;
+        const int2 w = B.items[it];
+        const BatchProb& P = B.probs[w.x];
+        const int deg = P.degree;
+        if (deg != cur) {   // uniform: all threads read the same item
+            const int ntab = kTabPerUnit * (deg + 1) / 2 + 1;
+            for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = P.f.tab[e];
+            cur = deg;
+            __syncthreads();
+        }
+        const int nb = (int)((P.f.m + B.lines_per_item - 1) / B.lines_per_item);
+        const int st = w.y / nb, blk = w.y - st * nb;
+        const int64_t base = (int64_t)blk * B.lines_per_item;
+        for (int sub = 0; sub < B.lines_per_item; sub += kBlock) {
+            const int64_t k0 = base + sub;
+            if (k0 >= P.f.m) break;
+            switch (deg) {
+            case 0: fwd_block_any<0>(P, k0, st, s_tab); break;
+            case 1: fwd_block_any<1>(P, k0, st, s_tab); break;
+            case 2: fwd_block_any<2>(P, k0, st, s_tab); break;
+            default: fwd_block_any<3>(P, k0, st, s_tab); break;
+            }
+        }
+    }
+}
+
+// sino[idx[k]] = (sum of the strips' sums of line k) * h / max(|cos|,|sin|),
+// 0 for lines that miss the grid; one launch per problem
+__global__ void __launch_bounds__(kBlock) k_batch_fwd_reduce(const BatchProb* probs, int p)
+{
+    const BatchProb& P = probs[p];
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= P.f.m) return;
+    float v = 0.f;
+    if (k < P.m_valid) {
+        const int ns = k < P.m_vert ? P.f.strips_v : P.f.strips_h;
+        double acc = 0.0;
+        for (int st = 0; st < ns; ++st) acc += (double)P.spart[(int64_t)st * P.f.m + k];
+        const double kap = P.f.kap[k];
+        const int n = P.degree;
+        const double ts = n == 3 ? (double)tap_scale<3>() : n == 2 ? (double)tap_scale<2>()
+                        : n == 1 ? (double)tap_scale<1>() : (double)tap_scale<0>();
+        v = (float)(acc * P.f.h * sqrt(1.0 + kap * kap) / ts);
+    }
+    P.f.sino[P.f.idx[k]] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs B)
+{
+    __shared__ AdjShared sh;
+    __shared__ int s_item;
+    int cur = -1;
+    for (;;) {
+        const int it = next_item(B.counter, &s_item);
+        if (it >= B.nitems) break;
+        const int2 w = B.items[it];
+        const BatchProb& P = B.probs[w.x];
+        const int deg = P.degree;
+        if (deg != cur) {
+            const int ntab = kTabPerUnit * (deg + 1) / 2 + 1;
+            for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = P.a.tab[e];
+            cur = deg;
+            __syncthreads();
+        }
+        switch (deg) {
+        case 0: adj_tile<0>(P.a, w.y, 0, sh); break;
+        case 1: adj_tile<1>(P.a, w.y, 0, sh); break;
+        case 2: adj_tile<2>(P.a, w.y, 0, sh); break;
+        default: adj_tile<3>(P.a, w.y, 0, sh); break;
+        }
+    }
+}
+
+__global__ void k_reset_counter(unsigned int* c) { c[threadIdx.x] = 0u; }
 
 // ---------------------------------------------------------------- nnz
 struct NnzArgs {
@@ -1020,8 +1220,7 @@ static hipError_t layouts_n(const xrt_plan* p, const float* coeffs, hipStream_t 
     return hipGetLastError();
 }
 
-template <int N>
-static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
+static FwdArgs make_fwd_args(const xrt_plan* p, float* sino)
 {
     FwdArgs a;
     a.m = p->m;
@@ -1043,11 +1242,44 @@ static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
     a.part = p->part;
     a.strips_v = p->strips_v;
     a.strips_h = p->strips_h;
+    a.strip = 0;
+    a.concurrent = 0;
+    a.nblk = (int)((p->m + kBlock - 1) / kBlock);
+    a.nblk_pad = (a.nblk + 7) / 8 * 8;
+    return a;
+}
+
+static AdjArgs make_adj_args(const xrt_plan* p, float* out)
+{
+    AdjArgs a;
+    a.xc = p->xc;
+    a.kap = p->kap;
+    a.sw = p->sw;
+    a.off = p->off;
+    a.tab = p->tab;
+    a.nx = p->g.nx;
+    a.ny = p->g.ny;
+    a.nbk_v = p->nbk_v;
+    a.nbk_h = p->nbk_h;
+    a.boff_v = p->boff_v;
+    a.boff_h = p->boff_h;
+    a.tiles_i = (p->g.nx + kTileI - 1) / kTileI;
+    a.tiles_j = (p->g.ny + kTileJ - 1) / kTileJ;
+    a.ntiles = a.tiles_i * a.tiles_j;
+    a.ntiles_pad = (a.ntiles + 7) / 8 * 8;
+    a.out = out;
+    a.split = 1;
+    a.part = nullptr;
+    return a;
+}
+
+template <int N>
+static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
+{
+    FwdArgs a = make_fwd_args(p, sino);
     // the split between vertical and horizontal lines is known on the device
     // only: the grid of each launch covers all m lines and blocks past the
     // launch's range return at once
-    a.nblk = (int)((p->m + kBlock - 1) / kBlock);
-    a.nblk_pad = (a.nblk + 7) / 8 * 8;
     a.concurrent = p->fwd_conc;
     a.strip = 0;
     if (p->fwd_conc) {
@@ -1095,23 +1327,7 @@ hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, h
 template <int N>
 static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
 {
-    AdjArgs a;
-    a.xc = p->xc;
-    a.kap = p->kap;
-    a.sw = p->sw;
-    a.off = p->off;
-    a.tab = p->tab;
-    a.nx = p->g.nx;
-    a.ny = p->g.ny;
-    a.nbk_v = p->nbk_v;
-    a.nbk_h = p->nbk_h;
-    a.boff_v = p->boff_v;
-    a.boff_h = p->boff_h;
-    a.tiles_i = (p->g.nx + kTileI - 1) / kTileI;
-    a.tiles_j = (p->g.ny + kTileJ - 1) / kTileJ;
-    a.ntiles = a.tiles_i * a.tiles_j;
-    a.ntiles_pad = (a.ntiles + 7) / 8 * 8;
-    a.out = out;
+    AdjArgs a = make_adj_args(p, out);
     a.split = p->adj_split;
     a.part = p->adj_part;
     hipLaunchKernelGGL(k_adjoint<N>, dim3((unsigned)a.ntiles_pad, (unsigned)a.split), dim3(kBlock), 0, s, a);
@@ -1123,7 +1339,7 @@ static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s)
+static hipError_t sort_sino(const xrt_plan* p, const float* sino, hipStream_t s)
 {
     if (p->m > 0) {
         SortSinoArgs a;
@@ -1136,9 +1352,15 @@ hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipS
         a.sw = p->sw;
         hipLaunchKernelGGL(k_sort_sino, dim3((unsigned)((p->m + kBlock - 1) / kBlock)), dim3(kBlock),
                            0, s, a);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        return hipGetLastError();
     }
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s)
+{
+    hipError_t e = sort_sino(p, sino, s);
+    if (e != hipSuccess) return e;
     switch (p->degree) {
     case 0: return adjoint_n<0>(p, out, s);
     case 1: return adjoint_n<1>(p, out, s);
@@ -1160,6 +1382,77 @@ hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s)
     a.degree = p->degree;
     a.out = out;
     hipLaunchKernelGGL(k_nnz, dim3((unsigned)((p->m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batch (host side)
+size_t batch_prob_size() { return sizeof(BatchProb); }
+
+int batch_strips(const xrt_plan* p) { return p->strips_v > p->strips_h ? p->strips_v : p->strips_h; }
+
+void batch_fill(const xrt_plan* p, float* sino, float* back, float* spart, void* dst)
+{
+    BatchProb b;
+    b.f = make_fwd_args(p, sino);
+    b.a = make_adj_args(p, back);
+    b.degree = p->degree;
+    b.nstrip = batch_strips(p);
+    b.m_vert = p->m_vert;
+    b.m_valid = p->m_valid;
+    b.spart = spart;
+    memcpy(dst, &b, sizeof(b));
+}
+
+hipError_t launch_batch_fwd_reduce(const void* probs, int p, int64_t m, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_fwd_reduce, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       static_cast<const BatchProb*>(probs), p);
+    return hipGetLastError();
+}
+
+hipError_t launch_layouts(const xrt_plan* p, const float* coeffs, hipStream_t s)
+{
+    if (p->m == 0) return hipSuccess;
+    switch (p->degree) {
+    case 0: return layouts_n<0>(p, coeffs, s);
+    case 1: return layouts_n<1>(p, coeffs, s);
+    case 2: return layouts_n<2>(p, coeffs, s);
+    default: return layouts_n<3>(p, coeffs, s);
+    }
+}
+
+hipError_t launch_sort_sino(const xrt_plan* p, const float* sino, hipStream_t s) { return sort_sino(p, sino, s); }
+
+hipError_t launch_reset_counters(unsigned int* c, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3((unsigned)n), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_forward(const void* probs, const int2* items, int nitems, unsigned int* counter,
+                                int lines_per_item, int grid, hipStream_t s)
+{
+    BatchArgs b;
+    b.probs = static_cast<const BatchProb*>(probs);
+    b.items = items;
+    b.nitems = nitems;
+    b.counter = counter;
+    b.lines_per_item = lines_per_item;
+    hipLaunchKernelGGL(k_batch_forward, dim3((unsigned)grid), dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adjoint(const void* probs, const int2* items, int nitems, unsigned int* counter, int grid,
+                                hipStream_t s)
+{
+    BatchArgs b;
+    b.probs = static_cast<const BatchProb*>(probs);
+    b.items = items;
+    b.nitems = nitems;
+    b.counter = counter;
+    b.lines_per_item = kBlock;
+    hipLaunchKernelGGL(k_batch_adjoint, dim3((unsigned)grid), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 

@@ -143,3 +143,28 @@ def test_learn_entry_points_reject_bad_arguments():
     assert lib.xrt_conv3x3_forward(1, 1, 1, 8, 8, 16, 32, 0, 1, None) == L.XRT_EINVAL
     assert lib.xrt_conv3x3_grad_weight(1, 1, 1, 8, 8, 32, 48, 1, None) == L.XRT_EINVAL
     assert lib.xrt_conv3x3_grad_input(None, 1, 1, 8, 8, 32, 32, 1, None) == L.XRT_EINVAL
+
+
+# ------------------------------------------------------------ include/xrt_batch.h
+def test_batch_entry_points_reject_bad_arguments():
+    lib = L.load()
+    out = ctypes.c_void_p()
+    assert lib.xrt_batch_create(None, 1, None, ctypes.byref(out)) == L.XRT_EINVAL
+    probs = (L.XrtProblem * 1)()
+    assert lib.xrt_batch_create(probs, 0, None, ctypes.byref(out)) == L.XRT_EINVAL
+    assert lib.xrt_batch_create(probs, 1, None, None) == L.XRT_EINVAL
+    # a problem with an invalid degree fails in its plan, before any device work
+    probs[0].grid = grid()
+    probs[0].degree = 7
+    probs[0].lines = L.XrtLines(0, 0, None, None, None)
+    assert lib.xrt_batch_create(probs, 1, None, ctypes.byref(out)) == L.XRT_EDEGREE
+    assert out.value is None
+    cfg = L.XrtBatchConfig(4, 256, 2, 0)
+    assert lib.xrt_batch_forward(None, None) == L.XRT_EINVAL
+    assert lib.xrt_batch_adjoint(None, None) == L.XRT_EINVAL
+    assert lib.xrt_batch_run(None, 1, None) == L.XRT_EINVAL
+    assert lib.xrt_batch_set_config(None, ctypes.byref(cfg)) == L.XRT_EINVAL
+    assert lib.xrt_batch_get_config(None, ctypes.byref(cfg)) == L.XRT_EINVAL
+    assert lib.xrt_batch_autotune(None, 1, None, None) == L.XRT_EINVAL
+    assert lib.xrt_batch_info(None, None, None, None) == L.XRT_EINVAL
+    assert lib.xrt_batch_buffers(None, 0, None, None, None) == L.XRT_EINVAL

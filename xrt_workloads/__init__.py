@@ -254,3 +254,31 @@ def training_fields(count: int, H: int, W: int, seed: int, device="cpu"):
         rms = torch.sqrt(torch.mean(img * img))
         out[i] = img / rms if float(rms) > 0 else img
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batches of uneven problems
+# ---------------------------------------------------------------------------
+
+
+def batch_problems(count: int = 64, seed: int = 21, sizes=(128, 256, 512, 1024), degrees=(1, 3),
+                   angles=(60, 720), phantoms: bool = True):
+    """`count` problems of uneven size: N drawn from `sizes`, degree from
+    `degrees`, the number of views U{angles}, parallel beam or fan beam with
+    equal probability, ceil(1.5 N) unit-spaced bins (parallel) or bins on the
+    arc (fan, source radius 2N).  Returns a list of dicts with N, degree,
+    kind, spec (lines), and the phantom (30 ellipses + texture)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        N = int(rng.choice(sizes))
+        n = int(rng.choice(degrees))
+        na = int(rng.integers(angles[0], angles[1] + 1))
+        nb = int(math.ceil(1.5 * N))
+        if rng.random() < 0.5:
+            spec, kind = parallel_beam(na, nb), "parallel"
+        else:
+            spec, kind = fan_beam(na, nb, 2.0 * N, N, n), "fan"
+        out.append({"N": N, "degree": n, "kind": kind, "views": na, "bins": nb, "spec": spec,
+                    "phantom": ellipse_phantom(N, 30, seed * 1000 + i, texture_sigma=0.1) if phantoms else None})
+    return out
