@@ -11,7 +11,10 @@ Tikhonov normal equations (lambda 1e-2) on a 512 x 512 cubic grid with
 180 x 768 parallel-beam Poisson-noisy data, plain CG against flexible CG with
 the trained U-Net preconditioner (training time reported separately).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--no-recon]
+It also carries "batch": 64 uneven problems in one persistent launch per
+direction (with graph replay and the autotuner) against per-problem plans.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--no-recon] [--no-batch]
 """
 from __future__ import annotations
 
@@ -159,6 +162,67 @@ def recon_leg(log):
             "rel_residual": {"cg": cg["rel_residual"], "learned": ln["rel_residual"]}}
 
 
+def batch_leg(log):
+    """64 uneven problems (sizes 128..1024, degrees 1 and 3, 60..720 views,
+    parallel or fan): per-problem plans one after another vs one persistent
+    launch per direction, eager and replayed as a HIP graph, before and after
+    the autotuner.  Rates in lines per second over the whole batch."""
+    import torch
+
+    import xrt_workloads as W
+    from paper_2503_20907_amd import batch, ops
+    probs = W.batch_problems(64, phantoms=False)
+    lines = [ops.Lines.from_spec(p["spec"]) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = batch.Batch([(p["N"], p["N"], p["degree"], l) for p, l in zip(probs, lines)])
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    g = torch.Generator(device="cuda").manual_seed(0)
+    for k in range(len(b)):
+        b.coeffs(k).normal_(generator=g)
+    plans = [ops.Plan(p["N"], p["N"], p["degree"], l) for p, l in zip(probs, lines)]
+    sinos = [torch.empty(l.n, device="cuda") for l in lines]
+    backs = [torch.empty(p["N"], p["N"], device="cuda") for p in probs]
+
+    def seq():
+        for k, pl in enumerate(plans):
+            pl.forward(b.coeffs(k), sinos[k])
+            pl.adjoint(sinos[k], backs[k])
+
+    def timeit(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3
+
+    M = b.info()["lines"]
+    out = {"workload": "64 problems: N in {128,256,512,1024}, degree in {1,3}, 60-720 views, "
+                       "ceil(1.5N) bins, parallel or fan (seed 21)",
+           "lines": int(M), "create_ms": round(create_ms, 1)}
+    out["sequential_plans_ms"] = round(timeit(seq), 3)
+    out["batch_ms_default"] = round(timeit(lambda: b.run(graph=False)), 3)
+    t0 = time.perf_counter()
+    out["autotuned_config"] = b.autotune(reps=2)
+    out["autotune_s"] = round(time.perf_counter() - t0, 2)
+    out["batch_ms"] = round(timeit(lambda: b.run(graph=False)), 3)
+    out["batch_graph_ms"] = round(timeit(lambda: b.run(graph=True)), 3)
+    out["batch_fwd_ms"] = round(timeit(b.forward), 3)
+    out["batch_adj_ms"] = round(timeit(b.adjoint), 3)
+    best = min(out["batch_ms"], out["batch_graph_ms"])
+    out["gray_per_s"] = round(M / (best / 1e3) / 1e9, 5)
+    out["speedup_vs_sequential"] = round(out["sequential_plans_ms"] / best, 3)
+    log(f"[bench] batch: sequential {out['sequential_plans_ms']} ms, batched {out['batch_ms']} ms, "
+        f"graph {out['batch_graph_ms']} ms, config {out['autotuned_config']}")
+    for pl in plans:
+        pl.close()
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +230,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction (learned vs CG) leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
     ap.add_argument("--n-src", type=int, default=1440)
     ap.add_argument("--n-bins", type=int, default=3072)
     ap.add_argument("--grid", type=int, default=2048)
@@ -284,6 +349,8 @@ def main():
     }
     plan.close()
     del sino, back
+    if not args.no_batch:
+        result["batch"] = batch_leg(lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_recon:
         result["recon"] = recon_leg(lambda msg: print(msg, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
