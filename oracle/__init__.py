@@ -17,6 +17,9 @@ point states the passage of the paper it follows:
   forward), ray-major in FP64.
 * ``adjoint_pixels``: the same quantity at selected pixels only.
 * ``nnz``: the number of (line, centre) pairs inside the footprint support.
+* ``n = BOX3`` anywhere a degree is taken: the 3-directional box spline of
+  Section III-C (directions e1, e2, e1 + e2); its footprint is the exact line
+  integral of the spatial box spline (a hat on a hexagon).
 """
 from __future__ import annotations
 
@@ -66,6 +69,10 @@ def _load():
         f.restype = ctypes.c_double
     lib.orc_bspline.argtypes = [ctypes.c_int, ctypes.c_double]
     lib.orc_bspline.restype = ctypes.c_double
+    lib.orc_box_spline.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.orc_box_spline.restype = ctypes.c_double
+    lib.orc_footprint_box.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.orc_footprint_box.restype = ctypes.c_double
     lib.orc_lines_theta_y.argtypes = [i64, fp, fp, dp, dp, dp]
     lib.orc_lines_endpoints.argtypes = [i64, fp, dp, dp, dp]
     lib.orc_forward.argtypes = [ctypes.c_int, gp, dp, i64, dp, dp, dp, dp, ctypes.c_int]
@@ -98,8 +105,17 @@ def bspline(n: int, x) -> np.ndarray:
     return np.array([lib.orc_bspline(int(n), float(v)) for v in xs])
 
 
+BOX3 = 16   # basis code of the 3-directional box spline (directions e1, e2, e1+e2)
+
+
+def box_spline(x1, x2) -> float:
+    """The (uncentred) 3-directional box spline M(x) at one point."""
+    return float(_load().orc_box_spline(float(x1), float(x2)))
+
+
 def footprint(n: int, theta: float, u, method: str = "auto") -> np.ndarray:
-    """phi_theta(u) for the tensor B-spline of degree n, FP64."""
+    """phi_theta(u) for the tensor B-spline of degree n (or the box spline,
+    n = BOX3), FP64."""
     lib = _load()
     f = {"auto": lib.orc_footprint, "tp": lib.orc_footprint_tp,
          "gl": lib.orc_footprint_gl}[method]

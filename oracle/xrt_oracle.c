@@ -87,10 +87,64 @@ static double factorial(int n)
     return r;
 }
 
-/* Support half-width of phi_theta: (n+1)(a+b)/2. */
-static double support_halfwidth(int n, double a, double b)
+/* Basis code of the 3-directional box spline (directions e1, e2, e1+e2),
+ * Section III-C; degrees 0..3 are the tensor-product B-splines. */
+#define ORC_BOX3 16
+
+/* Support half-width of phi_theta (c = cos, s = sin, signed):
+ * B-splines (n+1)(|c|+|s|)/2; the box spline (|s| + |c| + |s - c|)/2, half
+ * the summed widths |<theta_perp, u_d>| of its three directions. */
+static double support_halfwidth(int n, double c, double s)
 {
-    return 0.5 * (double)(n + 1) * (a + b);
+    if (n == ORC_BOX3) return 0.5 * (fabs(s) + fabs(c) + fabs(s - c));
+    return 0.5 * (double)(n + 1) * (fabs(c) + fabs(s));
+}
+
+/* --------------------------------------------- box spline, in space
+ * M(x) = int_0^1 1_[0,1]^2(x - t(1,1)) dt = max(0, min(1, x1, x2) - max(0, x1-1, x2-1)),
+ * the box spline of the directions e1, e2, e1+e2 (a hat on a hexagon, value
+ * 1 at the centre (1,1)); centred: Mc(x) = M(x + (1,1)). */
+double orc_box_spline(double x1, double x2)
+{
+    double lo = fmax(0.0, fmax(x1 - 1.0, x2 - 1.0));
+    double hi = fmin(1.0, fmin(x1, x2));
+    return fmax(0.0, hi - lo);
+}
+
+/* Footprint of the centred box spline: the line integral
+ *   phi_theta(u) = int Mc(t theta + u theta_perp) dt,  theta = (c, s), theta_perp = (s, -c),
+ * computed exactly: along the line Mc is piecewise linear in t with kinks only
+ * where x1 = 0, x2 = 0 or x1 = x2, and zero for |t| > sqrt(2); between
+ * consecutive kinks the positive part of a linear function is integrated in
+ * closed form. */
+double orc_footprint_box(double c, double s, double u)
+{
+    double pts[5];
+    int np = 0;
+    const double T = 2.0;
+    pts[np++] = -T;
+    if (c != 0.0) pts[np++] = -u * s / c;          /* x1 = t c + u s = 0 */
+    if (s != 0.0) pts[np++] = u * c / s;           /* x2 = t s - u c = 0 */
+    if (c != s) pts[np++] = -u * (s + c) / (c - s); /* x1 = x2 */
+    pts[np++] = T;
+    /* sort and clip to [-T, T] */
+    for (int i = 1; i < np; ++i)
+        for (int k = i; k > 0 && pts[k] < pts[k - 1]; --k) {
+            double t = pts[k]; pts[k] = pts[k - 1]; pts[k - 1] = t;
+        }
+    double acc = 0.0;
+    for (int i = 0; i + 1 < np; ++i) {
+        double p = fmax(pts[i], -T), q = fmin(pts[i + 1], T);
+        if (!(q > p)) continue;
+        /* Mc = max(0, g), g = min(1, x1+1, x2+1) - max(0, x1, x2) linear on [p, q] */
+        double xp1 = p * c + u * s, xp2 = p * s - u * c, xq1 = q * c + u * s, xq2 = q * s - u * c;
+        double rp = fmin(1.0, fmin(xp1 + 1.0, xp2 + 1.0)) - fmax(0.0, fmax(xp1, xp2));
+        double rq = fmin(1.0, fmin(xq1 + 1.0, xq2 + 1.0)) - fmax(0.0, fmax(xq1, xq2));
+        if (rp >= 0.0 && rq >= 0.0) acc += 0.5 * (rp + rq) * (q - p);
+        else if (rp > 0.0) acc += 0.5 * rp * (q - p) * rp / (rp - rq);
+        else if (rq > 0.0) acc += 0.5 * rq * (q - p) * rq / (rq - rp);
+    }
+    return acc;
 }
 
 /* ------------------------------------------------ footprint, closed form
@@ -103,7 +157,7 @@ double orc_footprint_tp(int n, double c, double s, double u)
 {
     double a = fabs(c), b = fabs(s);
     if (n < 0 || n > 3 || !(a > 0.0) || !(b > 0.0)) return NAN;
-    double w = support_halfwidth(n, a, b);
+    double w = support_halfwidth(n, c, s);
     if (fabs(u) >= w) return 0.0;
     int p = 2 * n + 1;
     double acc = 0.0, comp = 0.0;
@@ -154,7 +208,7 @@ double orc_footprint_gl(int n, double c, double s, double u)
         /* the factor with zero scale is a Dirac (Proposition 1) */
         return orc_bspline(n, u / A) / A;
     }
-    if (fabs(u) >= support_halfwidth(n, a, b)) return 0.0;
+    if (fabs(u) >= support_halfwidth(n, c, s)) return 0.0;
     double pts[2 * 5 + 2];
     int np = 0;
     for (int k = 0; k <= n + 1; ++k) pts[np++] = (double)k - hw;          /* knots of beta(v) */
@@ -183,6 +237,7 @@ double orc_footprint_gl(int n, double c, double s, double u)
  * (min(|cos|,|sin|) >= 0.25), the quadrature otherwise. */
 double orc_footprint(int n, double c, double s, double u)
 {
+    if (n == ORC_BOX3) return orc_footprint_box(c, s, u);
     double B = fmin(fabs(c), fabs(s));
     if (B >= 0.25) return orc_footprint_tp(n, c, s, u);
     return orc_footprint_gl(n, c, s, u);
@@ -266,7 +321,7 @@ static void band(double t0, double dt, double lim, int kmax, int* lo, int* hi)
  * (rows when |sin| >= |cos|, columns otherwise) then minor index. */
 #define FOR_BAND(g, n, c, s, y, BODY)                                                    \
     do {                                                                                 \
-        double w_ = support_halfwidth((n), fabs(c), fabs(s));                            \
+        double w_ = support_halfwidth((n), (c), (s));                                    \
         if (fabs(s) >= fabs(c)) {                                                        \
             /* u = (y + x2 c - x1 s)/h ; x1 = cx + (i - ox) h  => u linear in i */      \
             for (int j = 0; j < (g)->ny; ++j) {                                          \
@@ -295,7 +350,7 @@ static void band(double t0, double dt, double lim, int kmax, int* lo, int* hi)
 
 static int check_args(int n, const orc_grid* g)
 {
-    if (n < 0 || n > 3) return ORC_EINVAL;
+    if ((n < 0 || n > 3) && n != ORC_BOX3) return ORC_EINVAL;
     if (!g || g->nx <= 0 || g->ny <= 0 || !(g->spacing > 0.0)) return ORC_EINVAL;
     return ORC_OK;
 }
@@ -419,7 +474,7 @@ int orc_adjoint_pixels(int n, const orc_grid* g, int64_t m, const double* cs, co
         for (int64_t r = 0; r < m; ++r) {
             double c = cs[r], s = sn[r];
             double u = offset_u(g, c, s, yy[r], i, j);
-            double w = support_halfwidth(n, fabs(c), fabs(s));
+            double w = support_halfwidth(n, c, s);
             if (fabs(u) > w * (1.0 + 1e-12)) continue;
             double f = orc_footprint(n, c, s, u);
             if (f != 0.0) nadd(&acc, sino[r] * f);
