@@ -50,12 +50,21 @@ extern "C" {
 typedef enum {
     XRT_OK = 0,
     XRT_EINVAL = -1,  /* null pointer, negative count, bad grid, non-finite or degenerate line */
-    XRT_EDEGREE = -2, /* degree outside 0..3 */
+    XRT_EDEGREE = -2, /* degree neither 0..3 nor XRT_BOX3 */
     XRT_ESIZE = -3,   /* grid or line count beyond the supported range */
     XRT_ENOMEM = -4,  /* device allocation failed; nothing is left allocated */
     XRT_EHIP = -5,    /* a HIP call or kernel launch failed */
     XRT_EPLAN = -6    /* plan and call disagree (null or foreign plan) */
 } xrt_status;
+
+/* Basis: `degree` 0..3 selects the tensor-product B-spline beta^n (x) beta^n
+ * (Section III-C, eq. (6)); XRT_BOX3 selects the 3-directional box spline of
+ * directions e1, e2, e1+e2 (Section III-C): centred, a piecewise-linear hat
+ * on a hexagon, phi(x) = max(0, min(1, x1+1, x2+1) - max(0, x1, x2)).  By
+ * Proposition 1 its footprint is the convolution of three centred unit-mass
+ * boxes of widths |<theta_perp, u_d>| = |sin t|, |cos t|, |sin t - cos t|
+ * (eq. (projbox) written for the line direction theta = (cos t, sin t)). */
+#define XRT_BOX3 16
 
 /* Coefficient grid.  nx, ny >= 1 and <= 32768; spacing h > 0 (the paper
  * takes h = 1); (cx, cy) is the centre of the grid of centres. */

@@ -22,6 +22,8 @@ XRT_ENOMEM = -4
 XRT_EHIP = -5
 XRT_EPLAN = -6
 
+XRT_BOX3 = 16   # basis code of the 3-directional box spline
+
 XRT_LINES_THETA_Y = 0
 XRT_LINES_ENDPOINTS = 1
 

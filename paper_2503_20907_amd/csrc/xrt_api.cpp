@@ -167,7 +167,7 @@ const char* xrt_status_string(xrt_status st)
     switch (st) {
     case XRT_OK: return "ok";
     case XRT_EINVAL: return "invalid argument";
-    case XRT_EDEGREE: return "degree must be 0, 1, 2 or 3";
+    case XRT_EDEGREE: return "degree must be 0, 1, 2, 3 or XRT_BOX3";
     case XRT_ESIZE: return "size out of the supported range";
     case XRT_ENOMEM: return "device memory allocation failed";
     case XRT_EHIP: return "HIP runtime error";
@@ -183,7 +183,7 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
 {
     if (!out) return XRT_EINVAL;
     *out = nullptr;
-    if (degree < 0 || degree > 3) return XRT_EDEGREE;
+    if (!valid_basis(degree)) return XRT_EDEGREE;
     xrt_status st = check_grid(g);
     if (st != XRT_OK) return st;
     st = check_lines(lines);
@@ -267,7 +267,7 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     hipError_t e = hipSuccess;
     const char* what = "plan";
     int ntab = 0;
-    const float* tab = etable_host(degree, &ntab);
+    const float* tab = etable_host(geom_degree(degree), &ntab);
 #define XRT_TRY(call, label)                 \
     do {                                     \
         if (e == hipSuccess) {               \
@@ -286,7 +286,7 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     ca.L.ep = lines->endpoints;
     ca.m = m;
     ca.g = p->g;
-    ca.degree = degree;
+    ca.degree = geom_degree(degree);
     ca.nbk_v = p->nbk_v;
     ca.nbk_h = p->nbk_h;
     ca.boff_v = p->boff_v;
@@ -411,7 +411,7 @@ xrt_status xrt_forward(const float* coeffs, xrt_grid g, int degree, const xrt_li
                        float* sino, void* stream)
 {
     if (!coeffs || !lines) return XRT_EINVAL;
-    if (degree < 0 || degree > 3) return XRT_EDEGREE;
+    if (!valid_basis(degree)) return XRT_EDEGREE;
     xrt_status st = check_grid(g);
     if (st != XRT_OK) return st;
     st = check_lines(lines);
@@ -434,7 +434,7 @@ xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xr
                        float* coeffs_out, void* stream)
 {
     if (!coeffs_out || !lines) return XRT_EINVAL;
-    if (degree < 0 || degree > 3) return XRT_EDEGREE;
+    if (!valid_basis(degree)) return XRT_EDEGREE;
     xrt_status st = check_grid(g);
     if (st != XRT_OK) return st;
     st = check_lines(lines);

@@ -117,6 +117,12 @@ const float* etable_host(int n, int* n_entries);
 }  // namespace xrt
 
 namespace xrt {
+// basis code of the 3-directional box spline (Section III-C); plans of it use
+// the degree-1 margins for canonicalisation and binning (its row window,
+// 1 + |kappa| columns, is within the degree-1 one)
+constexpr int kBox3 = 16;
+inline bool valid_basis(int d) { return (d >= 0 && d <= 3) || d == kBox3; }
+inline int geom_degree(int d) { return d == kBox3 ? 1 : d; }
 // message returned by xrt_last_error() on this thread
 void set_last_error(const char* msg);
 }  // namespace xrt

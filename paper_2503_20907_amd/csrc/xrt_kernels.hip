@@ -466,6 +466,72 @@ __device__ inline int xcd_logical(int bid, int nblk_pad)
     return (bid % 8) * per + bid / 8;
 }
 
+// ---------------------------------------------------------------- box spline
+// Footprint of the 3-directional box spline (directions e1, e2, e1+e2): by
+// Proposition 1 the convolution of three centred unit-mass boxes of widths
+// |<theta_perp, u_d>| = |sin|, |cos|, |sin - cos|.  In terms of a line's slope
+// kappa (minor per major), with A = 1/sqrt(1+kappa^2) the major and
+// B = |kappa| A the minor direction cosine, the widths are A, B and A - B
+// (kappa >= 0: sin and cos of equal sign) or A + B (kappa < 0).  With w3 the
+// largest width (>= 1/sqrt(2)) and a <= b the other two,
+//   phi(u) = (F(u + w3/2) - F(u - w3/2)) / w3,
+// F the distribution function of the sum of two centred uniforms of widths a
+// and b (trapezoid density); nothing is divided by a small width.  u is the
+// distance of a centre from the line, |d| A for d its offset in minor cells.
+struct BoxConst {
+    float A;        // major direction cosine
+    float P, Q;     // (a + b)/2, (b - a)/2
+    float hb, invb; // b/2, 1/b
+    float inv2ab;   // 1/(2ab), 0 when a = 0
+    float w3h, invw3;
+};
+
+__device__ inline BoxConst box_const(double kap)
+{
+    const double A = 1.0 / sqrt(1.0 + kap * kap), B = fabs(kap) * A;
+    double a, b, w3;
+    if (kap >= 0.0) {
+        w3 = A;
+        a = fmin(B, A - B);
+        b = fmax(B, A - B);
+    } else {
+        w3 = A + B;
+        a = B;
+        b = A;
+    }
+    BoxConst k;
+    k.A = (float)A;
+    k.P = (float)(0.5 * (a + b));
+    k.Q = (float)(0.5 * (b - a));
+    k.hb = (float)(0.5 * b);
+    k.invb = (float)(1.0 / b);
+    k.inv2ab = a > 0.0 ? (float)(0.5 / (a * b)) : 0.f;
+    k.w3h = (float)(0.5 * w3);
+    k.invw3 = (float)(1.0 / w3);
+    return k;
+}
+
+// F(v) for v <= 0 (F(v) = 1 - F(-v) for v > 0)
+__device__ inline float trap_left(float v, const BoxConst& k)
+{
+    if (v <= -k.P) return 0.f;
+    if (v <= -k.Q) {
+        const float z = v + k.P;
+        return z * z * k.inv2ab;
+    }
+    return (v + k.hb) * k.invb;
+}
+
+__device__ inline float trap_cdf(float v, const BoxConst& k)
+{
+    return v <= 0.f ? trap_left(v, k) : 1.f - trap_left(-v, k);
+}
+
+__device__ inline float box_phi(float u, const BoxConst& k)
+{
+    return (trap_cdf(u + k.w3h, k) - trap_cdf(u - k.w3h, k)) * k.invw3;
+}
+
 // ---------------------------------------------------------------- forward
 struct FwdArgs {
     int64_t m;
@@ -628,6 +694,45 @@ __global__ void __launch_bounds__(kBlock) k_fwd_reduce(FwdArgs A)
     A.sino[A.idx[k]] = v;
 }
 
+// Box-spline forward: one thread per line over all its rows; the four
+// columns around each crossing are weighted by the footprint.  Lines that miss
+// the grid get 0.
+template <bool VERT>
+__device__ inline float fwd_box_line(const FwdArgs& A, double xc, double kap)
+{
+    const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
+    const double x0 = xc - kap * (0.5 * (nmaj - 1));
+    int ja, jb;
+    row_range(x0, kap, 1.0 + fabs(kap), nmaj, nmin, &ja, &jb);
+    if (ja > jb) return 0.f;
+    const BoxConst bk = box_const(kap);
+    const float* __restrict__ C = VERT ? A.cv : A.ch;
+    const int pitch = VERT ? A.pitch_v : A.pitch_h;
+    float acc = 0.f;
+    for (int j = ja; j <= jb; ++j) {
+        const double X = x0 + kap * (double)j;
+        const double fl = floor(X);
+        const float t = (float)(X - fl);
+        // columns i0-1 .. i0+2 (|X - i| < 2); the layout's zero padding covers
+        // the ones outside the grid
+        const float* row = C + (int64_t)j * pitch + kPad + (int)fl - 1;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) acc = fmaf(box_phi(fabsf(t - (float)(d - 1)) * bk.A, bk), row[d], acc);
+    }
+    return acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_forward_box(FwdArgs A)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= A.m) return;
+    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
+    float v = 0.f;
+    if (k < m_vert) v = fwd_box_line<true>(A, A.xc[k], A.kap[k]);
+    else if (k < m_valid) v = fwd_box_line<false>(A, A.xc[k], A.kap[k]);
+    A.sino[A.idx[k]] = (float)((double)v * A.h);
+}
+
 // ---------------------------------------------------------------- adjoint
 // Sinogram in sorted order, times h / max(|cos|, |sin|).
 struct SortSinoArgs {
@@ -638,6 +743,7 @@ struct SortSinoArgs {
     const float* sino;
     double h;
     float* sw;
+    int box;   // box basis: the footprint is not in row units, no slope factor
 };
 
 __global__ void __launch_bounds__(kBlock) k_sort_sino(SortSinoArgs A)
@@ -649,7 +755,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_sino(SortSinoArgs A)
         return;
     }
     double kap = A.kap[k];
-    A.sw[k] = (float)((double)A.sino[A.idx[k]] * A.h * sqrt(1.0 + kap * kap));
+    A.sw[k] = (float)((double)A.sino[A.idx[k]] * A.h * (A.box ? 1.0 : sqrt(1.0 + kap * kap)));
 }
 
 struct AdjArgs {
@@ -726,6 +832,48 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
         for (int sl = 0; sl < S; ++sl) atomicAdd(kr + sl, fixed_round(svkr, R.g[sl]));
         if (++jj == cnt) jj = 0;
     }
+}
+
+// Box spline: four columns per row around the crossing, weights from the
+// footprint, into the fixed-point LDS accumulator.
+__device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, float svs, const BoxConst& bk,
+                                    int W, int* s_a)
+{
+    int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
+    for (int c = 0; c < cnt; ++c) {
+        const double q = fma(kap, (double)jj, q0);
+        const double fl = floor(q);
+        const float t = (float)(q - fl);
+        const uint32_t rb = __umul24((uint32_t)(row0 + jj), (uint32_t)W);
+        int* ar = s_a + (rb + (uint32_t)((int)fl - 1));
+#pragma unroll
+        for (int d = 0; d < 4; ++d) atomicAdd(ar + d, fixed_round(svs, box_phi(fabsf(t - (float)(d - 1)) * bk.A, bk)));
+        if (++jj == cnt) jj = 0;
+    }
+}
+
+__device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, float sv, int e, bool vert, int maj0,
+                                    int min0, int TM, int TN, int nmaj, int W, double jc, double marg, int* s_a)
+{
+    if (!active) return;
+    const double xc = A.xc[k], kap = A.kap[k];
+    const double x0 = xc - kap * jc;
+    const int nmin = vert ? A.nx : A.ny;
+    int jlo, jhi;
+    row_range(x0, kap, 1.0 + fabs(kap), nmaj, nmin, &jlo, &jhi);
+    int ra = max(jlo, maj0), rb = min(jhi, maj0 + TM - 1);
+    if (kap != 0.0) {
+        double a = (min0 - marg - x0) / kap, b = (min0 + TN - 1 + marg - x0) / kap;
+        double lo2 = fmin(a, b), hi2 = fmax(a, b);
+        ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
+        rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
+    } else if (!(x0 >= min0 - marg && x0 <= min0 + TN - 1 + marg)) {
+        return;
+    }
+    if (ra > rb) return;
+    const BoxConst bk = box_const(kap);
+    const double q0 = x0 + kap * (double)ra - (double)min0 + (double)kHalo;
+    adj_walk_box(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
 }
 
 template <int N>
@@ -817,7 +965,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
     // nothing to the tile's outputs: its taps J-d (J = floor(X + (n+1)/2))
     // miss [min0, min0 + TN) and its knots (within (n+1)/2 of X + (n+1)/2)
     // miss [min0, min0 + TN + n]
-    const double marg = (double)N + 1.0;
+    const double marg = N == kBox3 ? 3.0 : (double)N + 1.0;
 
     float o[kPix];
 #pragma unroll
@@ -893,11 +1041,18 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
             if (!(mx > 0.f)) continue;  // uniform: nothing to add in this chunk
             int em;
             (void)frexpf(mx, &em);
-            const int e = 21 - em;  // |s| 2^e < 2^21
+            // |s| 2^e < 2^21 (B-splines: |w| <= 1); the box footprint reaches
+            // sqrt(2), one bit more headroom
+            const int e = (N == kBox3 ? 20 : 21) - em;
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-                adj_line<N>(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
-                            jc, marg, s_tab, s_a, s_k);
+            for (int u = 0; u < 2; ++u) {
+                if constexpr (N == kBox3)
+                    adj_line_box(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg,
+                                 s_a);
+                else
+                    adj_line<N>(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
+                                jc, marg, s_tab, s_a, s_k);
+            }
             __syncthreads();
             // flush: output += (A + Delta^T K) 2^-e  (forward difference of K)
 #pragma unroll
@@ -906,11 +1061,15 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                 const int pj = p / kTileI, pi = p % kTileI;  // pixel (row, column) in the tile
                 const int lmaj = vert ? pj : pi, lmin = vert ? pi : pj;
                 const int* ar = s_a + lmaj * W + kHalo + lmin;
-                const int* kr = s_k + lmaj * W + kHalo + lmin;
-                long long v = 0;
+                if constexpr (N == kBox3) {
+                    o[q] += ldexpf((float)ar[0], -e);
+                } else {
+                    const int* kr = s_k + lmaj * W + kHalo + lmin;
+                    long long v = 0;
 #pragma unroll
-                for (int l = 0; l <= N + 1; ++l) v += (long long)delta_w<N>(l) * kr[l];
-                o[q] += ldexpf((float)ar[0], -e) + ldexpf((float)v, -e - knot_shift<N>());
+                    for (int l = 0; l <= N + 1; ++l) v += (long long)delta_w<N>(l) * kr[l];
+                    o[q] += ldexpf((float)ar[0], -e) + ldexpf((float)v, -e - knot_shift<N>());
+                }
             }
             __syncthreads();
             for (int z = tid; z < TM * W; z += kBlock) {
@@ -937,8 +1096,10 @@ template <int N>
 __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
 {
     __shared__ AdjShared sh;
-    const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
-    for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
+    if constexpr (N != kBox3) {
+        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
+        for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
+    }
     const int tile = xcd_logical(blockIdx.x, A.ntiles_pad);
     if (tile >= A.ntiles) return;  // uniform per block
     adj_tile<N>(A, tile, (int)blockIdx.y, sh);
@@ -1126,7 +1287,10 @@ __global__ void __launch_bounds__(kBlock) k_nnz(NnzArgs A)
         const int nmaj = vert ? A.ny : A.nx, nmin = vert ? A.nx : A.ny;
         const double kap = A.kap[k];
         const double x0 = A.xc[k] - kap * (0.5 * (nmaj - 1));
-        const double W = 0.5 * (A.degree + 1) * (1.0 + fabs(kap));
+        // support half-width in minor cells: (n+1)(1 + |kappa|)/2 for B-splines;
+        // the box spline: 1 (kappa >= 0) or 1 + |kappa| (kappa < 0)
+        const double W = A.degree == kBox3 ? (kap >= 0.0 ? 1.0 : 1.0 + fabs(kap))
+                                           : 0.5 * (A.degree + 1) * (1.0 + fabs(kap));
         int jlo, jhi;
         row_range(x0, kap, W, nmaj, nmin, &jlo, &jhi);
         for (int j = jlo; j <= jhi; ++j) {
@@ -1315,6 +1479,13 @@ hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, h
 {
     if (p->m == 0) return hipSuccess;
     hipError_t e;
+    if (p->degree == kBox3) {
+        e = layouts_n<1>(p, coeffs, s);   // the coefficient layouts (the difference arrays go unused)
+        if (e != hipSuccess) return e;
+        FwdArgs a = make_fwd_args(p, sino);
+        hipLaunchKernelGGL(k_forward_box, dim3((unsigned)a.nblk), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
     switch (p->degree) {
     case 0: e = layouts_n<0>(p, coeffs, s); if (e == hipSuccess) e = forward_n<0>(p, sino, s); break;
     case 1: e = layouts_n<1>(p, coeffs, s); if (e == hipSuccess) e = forward_n<1>(p, sino, s); break;
@@ -1350,6 +1521,7 @@ static hipError_t sort_sino(const xrt_plan* p, const float* sino, hipStream_t s)
         a.sino = sino;
         a.h = p->g.h;
         a.sw = p->sw;
+        a.box = p->degree == kBox3 ? 1 : 0;
         hipLaunchKernelGGL(k_sort_sino, dim3((unsigned)((p->m + kBlock - 1) / kBlock)), dim3(kBlock),
                            0, s, a);
         return hipGetLastError();
@@ -1362,6 +1534,7 @@ hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipS
     hipError_t e = sort_sino(p, sino, s);
     if (e != hipSuccess) return e;
     switch (p->degree) {
+    case kBox3: return adjoint_n<kBox3>(p, out, s);
     case 0: return adjoint_n<0>(p, out, s);
     case 1: return adjoint_n<1>(p, out, s);
     case 2: return adjoint_n<2>(p, out, s);
