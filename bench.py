@@ -231,6 +231,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction (learned vs CG) leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems leg")
+    ap.add_argument("--no-box", action="store_true", help="skip the box-spline timing on the same lines")
     ap.add_argument("--n-src", type=int, default=1440)
     ap.add_argument("--n-bins", type=int, default=3072)
     ap.add_argument("--grid", type=int, default=2048)
@@ -348,6 +349,30 @@ def main():
         "rays_per_s": round(M / (ms_per_step / 1e3), 1),
     }
     plan.close()
+    if not args.no_box:
+        # the 3-directional box spline (the paper's recommended basis) on the same lines
+        bplan = ops.Plan(N, N, 16, lines)
+        for _ in range(2):
+            bplan.forward(c, sino)
+            bplan.adjoint(sino, back)
+        torch.cuda.synchronize()
+        evb = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(5)]
+        for k in range(5):
+            evb[k][0].record(stream)
+            bplan.forward(c, sino)
+            evb[k][1].record(stream)
+            bplan.adjoint(sino, back)
+            evb[k][2].record(stream)
+        torch.cuda.synchronize()
+        bf = float(np.median([evb[k][0].elapsed_time(evb[k][1]) for k in range(5)]))
+        ba = float(np.median([evb[k][1].elapsed_time(evb[k][2]) for k in range(5)]))
+        bnnz = bplan.nnz()
+        result["box3"] = {"basis": "3-directional box spline (e1, e2, e1+e2)", "t_fwd_ms": round(bf, 3),
+                          "t_adj_ms": round(ba, 3), "gray_per_s": round(M / ((bf + ba) / 1e3) / 1e9, 5),
+                          "nnz_per_pass": int(bnnz),
+                          "basis_evals_per_s": round(2 * bnnz / ((bf + ba) / 1e3), 1)}
+        print(f"[bench] box spline fwd {bf:.3f} ms, adj {ba:.3f} ms", file=sys.stderr, flush=True)
+        bplan.close()
     del sino, back
     if not args.no_batch:
         result["batch"] = batch_leg(lambda msg: print(msg, file=sys.stderr, flush=True))
