@@ -469,67 +469,62 @@ __device__ inline int xcd_logical(int bid, int nblk_pad)
 // ---------------------------------------------------------------- box spline
 // Footprint of the 3-directional box spline (directions e1, e2, e1+e2): by
 // Proposition 1 the convolution of three centred unit-mass boxes of widths
-// |<theta_perp, u_d>| = |sin|, |cos|, |sin - cos|.  In terms of a line's slope
-// kappa (minor per major), with A = 1/sqrt(1+kappa^2) the major and
-// B = |kappa| A the minor direction cosine, the widths are A, B and A - B
-// (kappa >= 0: sin and cos of equal sign) or A + B (kappa < 0).  With w3 the
-// largest width (>= 1/sqrt(2)) and a <= b the other two,
-//   phi(u) = (F(u + w3/2) - F(u - w3/2)) / w3,
-// F the distribution function of the sum of two centred uniforms of widths a
-// and b (trapezoid density); nothing is divided by a small width.  u is the
-// distance of a centre from the line, |d| A for d its offset in minor cells.
-struct BoxConst {
-    float A;        // major direction cosine
-    float P, Q;     // (a + b)/2, (b - a)/2
-    float hb, invb; // b/2, 1/b
-    float inv2ab;   // 1/(2ab), 0 when a = 0
-    float w3h, invw3;
+// |<theta_perp, u_d>| = |sin|, |cos|, |sin - cos|.  Measured along a row in
+// minor cells (distance = offset * A, A = 1/sqrt(1+kappa^2), kappa the slope
+// minor per major) the widths become 1, |kappa| and 1 - kappa (kappa >= 0) or
+// 1 + |kappa| (kappa < 0), and the footprint of a centre at offset v is
+// psi(v) / A with psi = box_1 * R, R the trapezoid density of the two other
+// widths a <= b (a + b = 1 for kappa >= 0, a = |kappa|, b = 1 + |kappa|
+// otherwise).  Since box_1 * R (v) = F(v + 1/2) - F(v - 1/2) with F the
+// distribution function of R, a row sum telescopes (summation by parts):
+//   sum_i c_i psi(X - i) = c_{i0-1} + sum_{d=0..2} F_d (c_{i0+d} - c_{i0+d-1}),
+// i0 = floor(X), t = X - i0, F_d = F at t + 1 + a' - d measured from the left
+// end of R's support, a' = |kappa| for kappa < 0 and 0 otherwise.  For
+// kappa >= 0 only F_1 = F(t) lies strictly between 0 and 1:
+// c_{i0} + F(t) (c_{i0+1} - c_{i0}), a two-tap row like linear interpolation.
+// The row sums then take the B-spline scaling h sqrt(1 + kappa^2).
+struct BoxRow {
+    float a, b, ab;       // trapezoid widths and a + b
+    float inv2a, invb;    // 1/(2a) (0 for a = 0), 1/b
+    float ha;             // a/2
+    float ofs;            // 1 + a'
+    int neg;              // kappa < 0: four columns per row
 };
 
-__device__ inline BoxConst box_const(double kap)
+__device__ inline BoxRow box_row(double kap)
 {
-    const double A = 1.0 / sqrt(1.0 + kap * kap), B = fabs(kap) * A;
-    double a, b, w3;
+    BoxRow k;
+    double a, b;
     if (kap >= 0.0) {
-        w3 = A;
-        a = fmin(B, A - B);
-        b = fmax(B, A - B);
+        a = fmin(kap, 1.0 - kap);
+        b = 1.0 - a;
     } else {
-        w3 = A + B;
-        a = B;
-        b = A;
+        a = -kap;
+        b = 1.0 - kap;
     }
-    BoxConst k;
-    k.A = (float)A;
-    k.P = (float)(0.5 * (a + b));
-    k.Q = (float)(0.5 * (b - a));
-    k.hb = (float)(0.5 * b);
+    k.a = (float)a;
+    if (!(k.a > 1e-30f)) k.a = 0.f;  // no overflow of 1/(2a); a term below 1e-30 is dropped
+    k.b = (float)b;
+    k.ab = (float)(a + b);
+    k.inv2a = k.a > 0.f ? (float)(0.5 / a) : 0.f;
     k.invb = (float)(1.0 / b);
-    k.inv2ab = a > 0.0 ? (float)(0.5 / (a * b)) : 0.f;
-    k.w3h = (float)(0.5 * w3);
-    k.invw3 = (float)(1.0 / w3);
+    k.ha = 0.5f * k.a;
+    k.neg = kap < 0.0 ? 1 : 0;
+    k.ofs = k.neg ? (float)(1.0 - kap) : 1.f;
     return k;
 }
 
-// F(v) for v <= 0 (F(v) = 1 - F(-v) for v > 0)
-__device__ inline float trap_left(float v, const BoxConst& k)
+// F(u), u from the left end of the support [0, a + b]: ramp of slope
+// 1/(ab) on [0, a], plateau 1/b on [a, b], ramp down on [b, a + b].  With
+// m = min(u, a) and n = min(a + b - u, a),
+//   F = (m^2/(2a) + (clamp(u, a, b) - a) + (a^2 - n^2)/(2a)) / b,
+// written so that nothing divides by a small width.
+__device__ inline float trap_F(float u, const BoxRow& k)
 {
-    if (v <= -k.P) return 0.f;
-    if (v <= -k.Q) {
-        const float z = v + k.P;
-        return z * z * k.inv2ab;
-    }
-    return (v + k.hb) * k.invb;
-}
-
-__device__ inline float trap_cdf(float v, const BoxConst& k)
-{
-    return v <= 0.f ? trap_left(v, k) : 1.f - trap_left(-v, k);
-}
-
-__device__ inline float box_phi(float u, const BoxConst& k)
-{
-    return (trap_cdf(u + k.w3h, k) - trap_cdf(u - k.w3h, k)) * k.invw3;
+    u = fminf(fmaxf(u, 0.f), k.ab);
+    const float m = fminf(u, k.a), n = fminf(k.ab - u, k.a);
+    const float cl = fminf(fmaxf(u, k.a), k.b);
+    return k.invb * fmaf((m - n) * (m + n), k.inv2a, cl - k.ha);
 }
 
 // ---------------------------------------------------------------- forward
@@ -588,6 +583,38 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     return part;
 }
 
+// Box-spline row sums over the rows [ja, jb] (q = X at row ja): two columns
+// per row, or four when the wave holds a line of negative slope (the
+// four-column form is exact for both signs).
+template <bool NEG>
+__device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const BoxRow& bk,
+                                     const float* __restrict__ C, int pitch)
+{
+    const char* __restrict__ Cb = (const char*)C;
+    uint32_t off = ((uint32_t)ja * (uint32_t)pitch + kPad) * 4u;
+    const uint32_t step = (uint32_t)pitch * 4u;
+    float part = 0.f;
+    for (int j = ja; j <= jb; ++j) {
+        const double fl = floor(q);
+        const float t = (float)(q - fl);
+        const uint32_t i0 = (uint32_t)(int)fl;
+        if constexpr (NEG) {
+            float c[4];
+            load_run<4>((const float*)(Cb + (off + (i0 - 1u) * 4u)), c);
+            const float u0 = t + bk.ofs;
+            const float F0 = trap_F(u0, bk), F1 = trap_F(u0 - 1.f, bk), F2 = trap_F(u0 - 2.f, bk);
+            part += fmaf(F2, c[3] - c[2], fmaf(F1, c[2] - c[1], fmaf(F0, c[1] - c[0], c[0])));
+        } else {
+            float c[2];
+            load_run<2>((const float*)(Cb + (off + i0 * 4u)), c);
+            part += fmaf(trap_F(t, bk), c[1] - c[0], c[0]);
+        }
+        q += kap;
+        off += step;
+    }
+    return part;
+}
+
 // Forward, one launch per (orientation, strip of kStrip rows): the blocks in
 // flight at any time read one strip of the layout, which stays in L2.  The
 // launches of one orientation run in strip order and each adds its partial
@@ -597,9 +624,11 @@ template <int N, bool VERT>
 __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
 {
     __shared__ float4 s_tab[kTabMax];
-    const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
-    for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
-    __syncthreads();
+    if constexpr (N != kBox3) {
+        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
+        for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
+        __syncthreads();
+    }
 
     int strip = A.strip;
     int bid = blockIdx.x;
@@ -625,20 +654,37 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     const int pitch = VERT ? A.pitch_v : A.pitch_h;
     const float* __restrict__ C = VERT ? A.cv : A.ch;
     const float* __restrict__ D = VERT ? A.dv : A.dh;
-    const double H = 0.5 * (N + 1);
     const double x0 = xc - kap * (0.5 * (nmaj - 1));
-    int jlo, jhi;
-    row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
-    const int ja = max(jlo, strip * kStrip), jb = min(jhi, strip * kStrip + kStrip - 1);
-    const LineConst lc = line_const<N>(kap);
-    const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
     float acc = 0.f;
-    if (ja <= jb) {
-        const double q0 = x0 + kap * (double)ja + H;
-        if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+    int ja, jb;
+    if constexpr (N == kBox3) {
+        // the footprint reaches 1 (kappa >= 0) or 1 + |kappa| minor cells
+        int jlo, jhi;
+        row_range(x0, kap, 1.0 + fabs(kap), nmaj, nmin, &jlo, &jhi);
+        ja = max(jlo, strip * kStrip);
+        jb = min(jhi, strip * kStrip + kStrip - 1);
+        const BoxRow bk = box_row(kap);
+        const bool neg = __ballot(ja <= jb && bk.neg) != 0ull;
+        if (ja <= jb) {
+            const double q0 = x0 + kap * (double)ja;
+            acc = neg ? fwd_walk_box<true>(q0, kap, ja, jb, bk, C, pitch)
+                      : fwd_walk_box<false>(q0, kap, ja, jb, bk, C, pitch);
+        }
+    } else {
+        const double H = 0.5 * (N + 1);
+        int jlo, jhi;
+        row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+        ja = max(jlo, strip * kStrip);
+        jb = min(jhi, strip * kStrip + kStrip - 1);
+        const LineConst lc = line_const<N>(kap);
+        const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
+        if (ja <= jb) {
+            const double q0 = x0 + kap * (double)ja + H;
+            if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+            else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+            else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+            else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+        }
     }
     if (A.concurrent) A.part[(int64_t)strip * A.m + k] = (double)acc;
     else if (strip == 0) A.part[k] = (double)acc;
@@ -694,45 +740,6 @@ __global__ void __launch_bounds__(kBlock) k_fwd_reduce(FwdArgs A)
     A.sino[A.idx[k]] = v;
 }
 
-// Box-spline forward: one thread per line over all its rows; the four
-// columns around each crossing are weighted by the footprint.  Lines that miss
-// the grid get 0.
-template <bool VERT>
-__device__ inline float fwd_box_line(const FwdArgs& A, double xc, double kap)
-{
-    const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
-    const double x0 = xc - kap * (0.5 * (nmaj - 1));
-    int ja, jb;
-    row_range(x0, kap, 1.0 + fabs(kap), nmaj, nmin, &ja, &jb);
-    if (ja > jb) return 0.f;
-    const BoxConst bk = box_const(kap);
-    const float* __restrict__ C = VERT ? A.cv : A.ch;
-    const int pitch = VERT ? A.pitch_v : A.pitch_h;
-    float acc = 0.f;
-    for (int j = ja; j <= jb; ++j) {
-        const double X = x0 + kap * (double)j;
-        const double fl = floor(X);
-        const float t = (float)(X - fl);
-        // columns i0-1 .. i0+2 (|X - i| < 2); the layout's zero padding covers
-        // the ones outside the grid
-        const float* row = C + (int64_t)j * pitch + kPad + (int)fl - 1;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) acc = fmaf(box_phi(fabsf(t - (float)(d - 1)) * bk.A, bk), row[d], acc);
-    }
-    return acc;
-}
-
-__global__ void __launch_bounds__(kBlock) k_forward_box(FwdArgs A)
-{
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= A.m) return;
-    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
-    float v = 0.f;
-    if (k < m_vert) v = fwd_box_line<true>(A, A.xc[k], A.kap[k]);
-    else if (k < m_valid) v = fwd_box_line<false>(A, A.xc[k], A.kap[k]);
-    A.sino[A.idx[k]] = (float)((double)v * A.h);
-}
-
 // ---------------------------------------------------------------- adjoint
 // Sinogram in sorted order, times h / max(|cos|, |sin|).
 struct SortSinoArgs {
@@ -743,7 +750,6 @@ struct SortSinoArgs {
     const float* sino;
     double h;
     float* sw;
-    int box;   // box basis: the footprint is not in row units, no slope factor
 };
 
 __global__ void __launch_bounds__(kBlock) k_sort_sino(SortSinoArgs A)
@@ -755,7 +761,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_sino(SortSinoArgs A)
         return;
     }
     double kap = A.kap[k];
-    A.sw[k] = (float)((double)A.sino[A.idx[k]] * A.h * (A.box ? 1.0 : sqrt(1.0 + kap * kap)));
+    A.sw[k] = (float)((double)A.sino[A.idx[k]] * A.h * sqrt(1.0 + kap * kap));
 }
 
 struct AdjArgs {
@@ -834,9 +840,11 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     }
 }
 
-// Box spline: four columns per row around the crossing, weights from the
-// footprint, into the fixed-point LDS accumulator.
-__device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, float svs, const BoxConst& bk,
+// Box spline: the row weights psi(X - i) = F_{i-i0} - F_{i-i0+1} of the
+// telescoped row sum (F_{-1} = 1, F_3 = 0) into the fixed-point LDS
+// accumulator: columns i0 and i0+1 for kappa >= 0, i0-1 .. i0+2 otherwise.
+template <bool NEG>
+__device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, float svs, const BoxRow& bk,
                                     int W, int* s_a)
 {
     int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
@@ -846,8 +854,18 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
         const float t = (float)(q - fl);
         const uint32_t rb = __umul24((uint32_t)(row0 + jj), (uint32_t)W);
         int* ar = s_a + (rb + (uint32_t)((int)fl - 1));
-#pragma unroll
-        for (int d = 0; d < 4; ++d) atomicAdd(ar + d, fixed_round(svs, box_phi(fabsf(t - (float)(d - 1)) * bk.A, bk)));
+        if constexpr (NEG) {
+            const float u0 = t + bk.ofs;
+            const float F0 = trap_F(u0, bk), F1 = trap_F(u0 - 1.f, bk), F2 = trap_F(u0 - 2.f, bk);
+            atomicAdd(ar, fixed_round(svs, 1.f - F0));
+            atomicAdd(ar + 1, fixed_round(svs, F0 - F1));
+            atomicAdd(ar + 2, fixed_round(svs, F1 - F2));
+            atomicAdd(ar + 3, fixed_round(svs, F2));
+        } else {
+            const float F = trap_F(t, bk);
+            atomicAdd(ar + 1, fixed_round(svs, 1.f - F));
+            atomicAdd(ar + 2, fixed_round(svs, F));
+        }
         if (++jj == cnt) jj = 0;
     }
 }
@@ -871,9 +889,10 @@ __device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, f
         return;
     }
     if (ra > rb) return;
-    const BoxConst bk = box_const(kap);
+    const BoxRow bk = box_row(kap);
     const double q0 = x0 + kap * (double)ra - (double)min0 + (double)kHalo;
-    adj_walk_box(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
+    if (bk.neg) adj_walk_box<true>(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
+    else adj_walk_box<false>(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
 }
 
 template <int N>
@@ -964,8 +983,8 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
     // a row whose crossing X lies outside (min0 - (n+1), min0 + TN + n) adds
     // nothing to the tile's outputs: its taps J-d (J = floor(X + (n+1)/2))
     // miss [min0, min0 + TN) and its knots (within (n+1)/2 of X + (n+1)/2)
-    // miss [min0, min0 + TN + n]
-    const double marg = N == kBox3 ? 3.0 : (double)N + 1.0;
+    // miss [min0, min0 + TN + n].  Box spline: columns floor(X)-1 .. floor(X)+2.
+    const double marg = N == kBox3 ? 2.0 : (double)N + 1.0;
 
     float o[kPix];
 #pragma unroll
@@ -985,7 +1004,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 
         for (int e = tid; e < TM * W; e += kBlock) {
             s_a[e] = 0;
-            s_k[e] = 0;
+            if constexpr (N != kBox3) s_k[e] = 0;
         }
         // candidate range of every slope bin: lines whose crossing of some
         // tile row falls within [min0 - marg, min0 + TN - 1 + marg]
@@ -1041,9 +1060,8 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
             if (!(mx > 0.f)) continue;  // uniform: nothing to add in this chunk
             int em;
             (void)frexpf(mx, &em);
-            // |s| 2^e < 2^21 (B-splines: |w| <= 1); the box footprint reaches
-            // sqrt(2), one bit more headroom
-            const int e = (N == kBox3 ? 20 : 21) - em;
+            // |s| 2^e < 2^21 (every row weight is at most 1)
+            const int e = 21 - em;
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if constexpr (N == kBox3)
@@ -1074,7 +1092,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
             __syncthreads();
             for (int z = tid; z < TM * W; z += kBlock) {
                 s_a[z] = 0;
-                s_k[z] = 0;
+                if constexpr (N != kBox3) s_k[z] = 0;
             }
             // the next chunk's block_max synchronises before its atomics
         }
@@ -1479,14 +1497,11 @@ hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, h
 {
     if (p->m == 0) return hipSuccess;
     hipError_t e;
-    if (p->degree == kBox3) {
-        e = layouts_n<1>(p, coeffs, s);   // the coefficient layouts (the difference arrays go unused)
-        if (e != hipSuccess) return e;
-        FwdArgs a = make_fwd_args(p, sino);
-        hipLaunchKernelGGL(k_forward_box, dim3((unsigned)a.nblk), dim3(kBlock), 0, s, a);
-        return hipGetLastError();
-    }
     switch (p->degree) {
+    case kBox3:  // the coefficient layouts only (the difference arrays go unused)
+        e = layouts_n<0>(p, coeffs, s);
+        if (e == hipSuccess) e = forward_n<kBox3>(p, sino, s);
+        break;
     case 0: e = layouts_n<0>(p, coeffs, s); if (e == hipSuccess) e = forward_n<0>(p, sino, s); break;
     case 1: e = layouts_n<1>(p, coeffs, s); if (e == hipSuccess) e = forward_n<1>(p, sino, s); break;
     case 2: e = layouts_n<2>(p, coeffs, s); if (e == hipSuccess) e = forward_n<2>(p, sino, s); break;
@@ -1521,7 +1536,6 @@ static hipError_t sort_sino(const xrt_plan* p, const float* sino, hipStream_t s)
         a.sino = sino;
         a.h = p->g.h;
         a.sw = p->sw;
-        a.box = p->degree == kBox3 ? 1 : 0;
         hipLaunchKernelGGL(k_sort_sino, dim3((unsigned)((p->m + kBlock - 1) / kBlock)), dim3(kBlock),
                            0, s, a);
         return hipGetLastError();
