@@ -3,8 +3,9 @@
  * persistent launch per direction, optionally replayed as a HIP graph, with
  * a run-time autotuner.  C ABI of libxrt.so.
  *
- * Each problem is what xrt_plan_create takes (a grid, a degree 0..3, a line
- * list, eq. (4) and its adjoint as in xrt.h); the batch builds one plan per
+ * Each problem is what xrt_plan_create takes (a grid, a degree 0..3 or
+ * XRT_BOX3, a line list, eq. (4) and its adjoint as in xrt.h); problems of
+ * different bases mix in one batch.  The batch builds one plan per
  * problem and owns, per problem, three device buffers: the coefficient image
  * (input of the forward), the sinogram (output of the forward, input of the
  * adjoint) and the back-projected image (output of the adjoint).  Their

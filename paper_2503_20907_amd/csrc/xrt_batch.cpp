@@ -156,9 +156,8 @@ xrt_status xrt_batch_create(const xrt_problem* problems, int32_t count, void* st
 {
     if (!problems || !out || count < 1) return XRT_EINVAL;
     *out = nullptr;
-    // the persistent kernels cover the tensor B-splines (degrees 0..3)
     for (int p = 0; p < count; ++p)
-        if (problems[p].degree < 0 || problems[p].degree > 3) return XRT_EDEGREE;
+        if (!xrt::valid_basis(problems[p].degree)) return XRT_EDEGREE;
     hipStream_t s = (hipStream_t)stream;
     xrt_batch* b = new xrt_batch();
     b->magic = kBatchMagic;

@@ -615,40 +615,14 @@ __device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const
     return part;
 }
 
-// Forward, one launch per (orientation, strip of kStrip rows): the blocks in
-// flight at any time read one strip of the layout, which stays in L2.  The
-// launches of one orientation run in strip order and each adds its partial
-// sums into part[k] (the first one writes), so the sum is deterministic;
-// k_fwd_reduce scales and scatters.
+// Sum of line k over the rows of strip `st` that it reaches (times
+// tap_scale<N>); [*ja, *jb] is that row range (empty when *ja > *jb).  The
+// lanes of a wave that call it together share the knot-slot count.
 template <int N, bool VERT>
-__global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
+__device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const float4* __restrict__ s_tab,
+                                      int* ja_out, int* jb_out)
 {
-    __shared__ float4 s_tab[kTabMax];
-    if constexpr (N != kBox3) {
-        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
-        for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
-        __syncthreads();
-    }
-
-    int strip = A.strip;
-    int bid = blockIdx.x;
-    if (A.concurrent) {
-        strip = blockIdx.x / A.nblk_pad;
-        bid = blockIdx.x - strip * A.nblk_pad;
-        if (strip >= (VERT ? A.strips_v : A.strips_h)) return;
-    }
-    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
-    // vertical lines are the sorted range [0, m_vert), horizontal ones
-    // [m_vert, m_valid).  The grid covers all m lines; the blocks of this
-    // launch's range are spread evenly over the XCDs and the rest return.
-    const int64_t first = VERT ? 0 : m_vert, end = VERT ? m_vert : m_valid;
-    const int nb = (int)((end - first + kBlock - 1) / kBlock);
-    const int nb_pad = (nb + 7) / 8 * 8;
-    if (bid >= nb_pad) return;
-    const int lb = xcd_logical(bid, nb_pad);
-    if (lb >= nb) return;
-    const int64_t k = first + (int64_t)lb * kBlock + threadIdx.x;
-    if (k >= end) return;
+    const int strip = st;
     const double xc = A.xc[k], kap = A.kap[k];
     const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
     const int pitch = VERT ? A.pitch_v : A.pitch_h;
@@ -686,37 +660,50 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
             else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
         }
     }
+    *ja_out = ja;
+    *jb_out = jb;
+    return acc;
+}
+
+// Forward, one launch per (orientation, strip of kStrip rows): the blocks in
+// flight at any time read one strip of the layout, which stays in L2.  The
+// launches of one orientation run in strip order and each adds its partial
+// sums into part[k] (the first one writes), so the sum is deterministic;
+// k_fwd_reduce scales and scatters.
+template <int N, bool VERT>
+__global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
+{
+    __shared__ float4 s_tab[kTabMax];
+    if constexpr (N != kBox3) {
+        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
+        for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
+        __syncthreads();
+    }
+
+    int strip = A.strip;
+    int bid = blockIdx.x;
+    if (A.concurrent) {
+        strip = blockIdx.x / A.nblk_pad;
+        bid = blockIdx.x - strip * A.nblk_pad;
+        if (strip >= (VERT ? A.strips_v : A.strips_h)) return;
+    }
+    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
+    // vertical lines are the sorted range [0, m_vert), horizontal ones
+    // [m_vert, m_valid).  The grid covers all m lines; the blocks of this
+    // launch's range are spread evenly over the XCDs and the rest return.
+    const int64_t first = VERT ? 0 : m_vert, end = VERT ? m_vert : m_valid;
+    const int nb = (int)((end - first + kBlock - 1) / kBlock);
+    const int nb_pad = (nb + 7) / 8 * 8;
+    if (bid >= nb_pad) return;
+    const int lb = xcd_logical(bid, nb_pad);
+    if (lb >= nb) return;
+    const int64_t k = first + (int64_t)lb * kBlock + threadIdx.x;
+    if (k >= end) return;
+    int ja, jb;
+    const float acc = fwd_strip_sum<N, VERT>(A, k, strip, s_tab, &ja, &jb);
     if (A.concurrent) A.part[(int64_t)strip * A.m + k] = (double)acc;
     else if (strip == 0) A.part[k] = (double)acc;
     else if (ja <= jb) A.part[k] += (double)acc;
-}
-
-// Line k over all its rows (no strips), scaled and written to the caller's
-// order: the per-line work of the batched forward.  Lanes of a wave that
-// call it together share the knot-slot count (wave_slots).
-template <int N, bool VERT>
-__device__ inline void fwd_line_full(const FwdArgs& A, int64_t k, const float4* __restrict__ s_tab)
-{
-    const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
-    const double H = 0.5 * (N + 1);
-    const double xc = A.xc[k], kap = A.kap[k];
-    const double x0 = xc - kap * (0.5 * (nmaj - 1));
-    int ja, jb;
-    row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &ja, &jb);
-    const LineConst lc = line_const<N>(kap);
-    const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
-    float acc = 0.f;
-    if (ja <= jb) {
-        const int pitch = VERT ? A.pitch_v : A.pitch_h;
-        const float* __restrict__ C = VERT ? A.cv : A.ch;
-        const float* __restrict__ D = VERT ? A.dv : A.dh;
-        const double q0 = x0 + kap * (double)ja + H;
-        if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-    }
-    A.sino[A.idx[k]] = (float)((double)acc * A.h * sqrt(1.0 + kap * kap) / (double)tap_scale<N>());
 }
 
 // sino[idx[k]] = (sum over strips of part[s][k]) * h / max(|cos|,|sin|);
@@ -1160,28 +1147,8 @@ struct BatchArgs {
 template <int N, bool VERT>
 __device__ inline void fwd_line_strip(const BatchProb& P, int64_t k, int st, const float4* __restrict__ s_tab)
 {
-    const FwdArgs& A = P.f;
-    const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
-    const double H = 0.5 * (N + 1);
-    const double xc = A.xc[k], kap = A.kap[k];
-    const double x0 = xc - kap * (0.5 * (nmaj - 1));
-    int jlo, jhi;
-    row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
-    const int ja = max(jlo, st * kStrip), jb = min(jhi, st * kStrip + kStrip - 1);
-    const LineConst lc = line_const<N>(kap);
-    const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
-    float acc = 0.f;
-    if (ja <= jb) {
-        const int pitch = VERT ? A.pitch_v : A.pitch_h;
-        const float* __restrict__ C = VERT ? A.cv : A.ch;
-        const float* __restrict__ D = VERT ? A.dv : A.dh;
-        const double q0 = x0 + kap * (double)ja + H;
-        if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-        else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-    }
-    P.spart[(int64_t)st * A.m + k] = acc;
+    int ja, jb;
+    P.spart[(int64_t)st * P.f.m + k] = fwd_strip_sum<N, VERT>(P.f, k, st, s_tab, &ja, &jb);
 }
 
 template <int N>
@@ -1215,7 +1182,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_forward(BatchArgs B)
         const BatchProb& P = B.probs[w.x];
         const int deg = P.degree;
         if (deg != cur) {   // uniform: all threads read the same item
-            const int ntab = kTabPerUnit * (deg + 1) / 2 + 1;
+            const int ntab = deg == kBox3 ? 0 : kTabPerUnit * (deg + 1) / 2 + 1;
             for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = P.f.tab[e];
             cur = deg;
             __syncthreads();
@@ -1230,7 +1197,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_forward(BatchArgs B)
             case 0: fwd_block_any<0>(P, k0, st, s_tab); break;
             case 1: fwd_block_any<1>(P, k0, st, s_tab); break;
             case 2: fwd_block_any<2>(P, k0, st, s_tab); break;
-            default: fwd_block_any<3>(P, k0, st, s_tab); break;
+            case 3: fwd_block_any<3>(P, k0, st, s_tab); break;
+            default: fwd_block_any<kBox3>(P, k0, st, s_tab); break;
             }
         }
     }
@@ -1249,7 +1217,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_fwd_reduce(const BatchProb* pr
         double acc = 0.0;
         for (int st = 0; st < ns; ++st) acc += (double)P.spart[(int64_t)st * P.f.m + k];
         const double kap = P.f.kap[k];
-        const int n = P.degree;
+        const int n = P.degree;  // the box spline's row sums are unscaled, as degrees 0..2
         const double ts = n == 3 ? (double)tap_scale<3>() : n == 2 ? (double)tap_scale<2>()
                         : n == 1 ? (double)tap_scale<1>() : (double)tap_scale<0>();
         v = (float)(acc * P.f.h * sqrt(1.0 + kap * kap) / ts);
@@ -1269,7 +1237,7 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs
         const BatchProb& P = B.probs[w.x];
         const int deg = P.degree;
         if (deg != cur) {
-            const int ntab = kTabPerUnit * (deg + 1) / 2 + 1;
+            const int ntab = deg == kBox3 ? 0 : kTabPerUnit * (deg + 1) / 2 + 1;
             for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = P.a.tab[e];
             cur = deg;
             __syncthreads();
@@ -1278,7 +1246,8 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs
         case 0: adj_tile<0>(P.a, w.y, 0, sh); break;
         case 1: adj_tile<1>(P.a, w.y, 0, sh); break;
         case 2: adj_tile<2>(P.a, w.y, 0, sh); break;
-        default: adj_tile<3>(P.a, w.y, 0, sh); break;
+        case 3: adj_tile<3>(P.a, w.y, 0, sh); break;
+        default: adj_tile<kBox3>(P.a, w.y, 0, sh); break;
         }
     }
 }
@@ -1605,7 +1574,8 @@ hipError_t launch_layouts(const xrt_plan* p, const float* coeffs, hipStream_t s)
     case 0: return layouts_n<0>(p, coeffs, s);
     case 1: return layouts_n<1>(p, coeffs, s);
     case 2: return layouts_n<2>(p, coeffs, s);
-    default: return layouts_n<3>(p, coeffs, s);
+    case 3: return layouts_n<3>(p, coeffs, s);
+    default: return layouts_n<0>(p, coeffs, s);  // box spline: the coefficient layouts only
     }
 }
 

@@ -168,13 +168,3 @@ def test_batch_entry_points_reject_bad_arguments():
     assert lib.xrt_batch_autotune(None, 1, None, None) == L.XRT_EINVAL
     assert lib.xrt_batch_info(None, None, None, None) == L.XRT_EINVAL
     assert lib.xrt_batch_buffers(None, 0, None, None, None) == L.XRT_EINVAL
-
-
-def test_batch_rejects_the_box_basis():
-    lib = L.load()
-    out = ctypes.c_void_p()
-    probs = (L.XrtProblem * 1)()
-    probs[0].grid = grid()
-    probs[0].degree = L.XRT_BOX3
-    probs[0].lines = L.XrtLines(0, 0, None, None, None)
-    assert lib.xrt_batch_create(probs, 1, None, ctypes.byref(out)) == L.XRT_EDEGREE

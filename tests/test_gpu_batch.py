@@ -23,12 +23,13 @@ def rel(a, b):
 
 @pytest.fixture(scope="module")
 def mixed():
-    """Eleven problems: sizes 1x1 .. 130x70, degrees 0-3, parallel, fan, random lines."""
+    """Thirteen problems: sizes 1x1 .. 130x70, degrees 0-3 and the box spline,
+    parallel, fan, random lines."""
     from paper_2503_20907_amd import batch, ops
     rng = np.random.default_rng(71)
     probs = []
     shapes = [(64, 64, 1), (130, 70, 3), (48, 100, 0), (96, 96, 2), (128, 128, 3), (1, 1, 1), (33, 17, 3),
-              (64, 80, 1), (100, 64, 3), (20, 20, 0), (128, 96, 2)]
+              (64, 80, 1), (100, 64, 3), (20, 20, 0), (128, 96, 2), (72, 56, oracle.BOX3), (50, 50, oracle.BOX3)]
     for i, (nx, ny, n) in enumerate(shapes):
         kind = i % 3
         N = max(nx, ny)
