@@ -801,6 +801,75 @@ __device__ inline int fixed_round(float a, float b)
     return __float_as_int(fmaf(a, b, kRoundMagic)) - kRoundMagicBits;
 }
 
+// The tap weights of tap_weights<N> times a line constant sigma, rounded to
+// integers as fixed_round does: the round-to-nearest-even constant
+// kRoundMagic is carried in per-line coefficients (and in the last
+// multiply-add of each weight), and sigma is folded into the coefficients,
+// so that a weight costs about what the unscaled one does.  Sums that pass
+// through kRoundMagic are rounded to integers on the way (at most three
+// roundings per weight, each to nearest even, so unbiased).
+template <int N>
+struct TapScaled {
+    float a, b, c, d, e, f;
+};
+
+template <int N>
+__device__ inline TapScaled<N> tap_scaled(float sigma, float rho)
+{
+    TapScaled<N> k;
+    k.a = k.b = k.c = k.d = k.e = k.f = 0.f;
+    if constexpr (N == 0) {
+        k.a = sigma + kRoundMagic;
+    } else if constexpr (N == 1) {
+        k.a = sigma;
+        k.b = sigma + kRoundMagic;
+    } else if constexpr (N == 2) {
+        k.a = sigma;
+        k.b = fmaf(sigma, rho, kRoundMagic);
+        k.c = fmaf(sigma, 0.75f - 2.f * rho, kRoundMagic);
+        k.d = 0.5f * sigma;
+    } else {
+        k.a = 0.5f * sigma;
+        k.b = sigma * rho;
+        k.c = sigma * (1.f / 6.f);
+        k.d = 6.f * rho;
+        k.e = fmaf(sigma, 2.f / 3.f, kRoundMagic);
+        k.f = fmaf(sigma, 1.f / 6.f, kRoundMagic);
+    }
+    return k;
+}
+
+__device__ inline int magic_int(float x) { return __float_as_int(x) - kRoundMagicBits; }
+
+// round(sigma * w[d]) for the taps J - d (d = 0..N)
+template <int N>
+__device__ inline void tap_fixed(float t, const TapScaled<N>& k, int* wi)
+{
+    if constexpr (N == 0) {
+        wi[0] = magic_int(k.a);
+    } else if constexpr (N == 1) {
+        wi[0] = magic_int(fmaf(k.a, t, kRoundMagic));
+        wi[1] = magic_int(fmaf(-k.a, t, k.b));
+    } else if constexpr (N == 2) {
+        // sigma (t^2/2 + rho), sigma (3/4 - 2 rho - (t - 1/2)^2), sigma ((1-t)^2/2 + rho)
+        const float u = t - 0.5f, s = 1.f - t;
+        wi[0] = magic_int(fmaf(k.d * t, t, k.b));
+        wi[1] = magic_int(fmaf(-k.a * u, u, k.c));
+        wi[2] = magic_int(fmaf(k.d * s, s, k.b));
+    } else {
+        // as tap_weights<3>, every term times sigma:
+        //   h2 = sigma (t^2 + 2 rho)/2, h3 = sigma t (t^2 + 6 rho)/6, u = sigma/6 + h2 - h3
+        const float ct = k.c * t, p = fmaf(t, t, k.d);
+        const float h3 = ct * p;
+        const float h2 = fmaf(k.a * t, t, k.b);
+        const float um = (k.f + h2) - h3;  // u + kRoundMagic
+        wi[0] = magic_int(fmaf(ct, p, kRoundMagic));
+        wi[3] = magic_int(fmaf(-k.a, t, um));
+        wi[1] = magic_int(fmaf(k.a, t, fmaf(-2.f, h3, um)));
+        wi[2] = magic_int(fmaf(3.f, h3, fmaf(-2.f, h2, k.e)));
+    }
+}
+
 template <int N, int S>
 __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float svs, float svk,
                                 const LineConst& lc, int W, const float4* __restrict__ s_tab,
@@ -810,17 +879,21 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     // update the same LDS word in one instruction
     int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
     const float svkr = svk * lc.rn;
+    const TapScaled<N> tk = tap_scaled<N>(svs, lc.rho);
+    // knot slots start at K0 = J + o, o = 1 - S/2 for even S (a constant), so
+    // that taps and slots share one base address at J - N
+    constexpr int kEven = 1 - S / 2 + N;
     for (int c = 0; c < cnt; ++c) {
         const double q = fma(kap, (double)jj, q0);
         Row<S> R;
         row_core<N, S>(q, lc, s_tab, R);
-        float w[N + 1];
-        tap_weights<N>(R.t, lc.rho, w);
-        const uint32_t rb = __umul24((uint32_t)(row0 + jj), (uint32_t)W);
-        int* ar = s_a + (rb + (uint32_t)(R.J - N));  // taps J-N .. J, ascending
-        int* kr = s_k + (rb + (uint32_t)R.K0);
+        int wi[N + 1];
+        tap_fixed<N>(R.t, tk, wi);
+        const uint32_t base = __umul24((uint32_t)(row0 + jj), (uint32_t)W) + (uint32_t)(R.J - N);
+        int* ar = s_a + base;  // taps J-N .. J, ascending
+        int* kr = s_k + base + (S % 2 == 0 ? (uint32_t)kEven : (uint32_t)(R.K0 - R.J + N));
 #pragma unroll
-        for (int d = 0; d <= N; ++d) atomicAdd(ar + d, fixed_round(svs, w[N - d]));
+        for (int d = 0; d <= N; ++d) atomicAdd(ar + d, wi[N - d]);
 #pragma unroll
         for (int sl = 0; sl < S; ++sl) atomicAdd(kr + sl, fixed_round(svkr, R.g[sl]));
         if (++jj == cnt) jj = 0;
@@ -897,18 +970,22 @@ __device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float
         x0 = xc - kap * jc;
         const int nmin = vert ? A.nx : A.ny;
         int jlo, jhi;
-        row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+        // rows whose crossing lies within the footprint's half-width
+        // H (1 + |kappa|) of the tile (at most marg)
+        const double ml = H * (1.0 + fabs(kap));
+        row_range(x0, kap, ml, nmaj, nmin, &jlo, &jhi);
         ra = max(jlo, maj0);
         rb = min(jhi, maj0 + TM - 1);
         if (kap != 0.0) {
-            double a = (min0 - marg - x0) / kap, b = (min0 + TN - 1 + marg - x0) / kap;
+            double a = (min0 - ml - x0) / kap, b = (min0 + TN - 1 + ml - x0) / kap;
             double lo2 = fmin(a, b), hi2 = fmax(a, b);
             ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
             rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
-        } else if (!(x0 >= min0 - marg && x0 <= min0 + TN - 1 + marg)) {
+        } else if (!(x0 >= min0 - ml && x0 <= min0 + TN - 1 + ml)) {
             rb = ra - 1;
         }
     }
+    (void)marg;
     const bool work = active && ra <= rb;
     const LineConst lc = line_const<N>(kap);
     const int S = wave_slots<N>(work ? lc.slots : 1);
