@@ -483,11 +483,21 @@ __device__ inline int xcd_logical(int bid, int nblk_pad)
 // kappa >= 0 only F_1 = F(t) lies strictly between 0 and 1:
 // c_{i0} + F(t) (c_{i0+1} - c_{i0}), a two-tap row like linear interpolation.
 // The row sums then take the B-spline scaling h sqrt(1 + kappa^2).
+//
+// R's density ramps up on [0, a], is flat (1/b) on [a, b] and ramps down on
+// [b, a + b].  With p = (a - t)_+ and q = (t + a - 1)_+ (the same
+// expressions for both signs):
+//   kappa >= 0 (b = 1 - a):  F(t) = (t - a/2)/b + (p^2 - q^2)/(2ab);
+//   kappa <  0 (b = 1 + a):  F_0 = 1 - p^2/(2ab) (ramp down),
+//                            F_1 = (t + a/2)/b (flat part),
+//                            F_2 = q^2/(2ab) (ramp up).
+// Both fit F_0 = 1 - k0 p^2, F_1 = t/b + c1 + k1 (p^2 - q^2), F_2 = k2 q^2
+// with per-line constants (kappa >= 0: k0 = k2 = 0; kappa < 0: k1 = 0).
+// For a -> 0 the p and q terms are O(a): nothing large is formed.
 struct BoxRow {
-    float a, b, ab;       // trapezoid widths and a + b
-    float inv2a, invb;    // 1/(2a) (0 for a = 0), 1/b
-    float ha;             // a/2
-    float ofs;            // 1 + a'
+    float a, am1;         // a, a - 1
+    float invb, c1;       // 1/b, -+a/(2b)
+    float k0, k1, k2;     // 1/(2ab) or 0 (see above)
     int neg;              // kappa < 0: four columns per row
 };
 
@@ -495,36 +505,40 @@ __device__ inline BoxRow box_row(double kap)
 {
     BoxRow k;
     double a, b;
-    if (kap >= 0.0) {
+    k.neg = kap < 0.0 ? 1 : 0;
+    if (!k.neg) {
         a = fmin(kap, 1.0 - kap);
         b = 1.0 - a;
     } else {
         a = -kap;
         b = 1.0 - kap;
     }
+    if (!(a > 1e-30)) a = 0.0;  // a term below 1e-30 is dropped
+    const float inv2ab = a > 0.0 ? (float)(0.5 / (a * b)) : 0.f;
     k.a = (float)a;
-    if (!(k.a > 1e-30f)) k.a = 0.f;  // no overflow of 1/(2a); a term below 1e-30 is dropped
-    k.b = (float)b;
-    k.ab = (float)(a + b);
-    k.inv2a = k.a > 0.f ? (float)(0.5 / a) : 0.f;
+    k.am1 = (float)(a - 1.0);
     k.invb = (float)(1.0 / b);
-    k.ha = 0.5f * k.a;
-    k.neg = kap < 0.0 ? 1 : 0;
-    k.ofs = k.neg ? (float)(1.0 - kap) : 1.f;
+    k.c1 = (float)((k.neg ? 0.5 : -0.5) * a / b);
+    k.k0 = k.neg ? inv2ab : 0.f;
+    k.k1 = k.neg ? 0.f : inv2ab;
+    k.k2 = k.neg ? inv2ab : 0.f;
     return k;
 }
 
-// F(u), u from the left end of the support [0, a + b]: ramp of slope
-// 1/(ab) on [0, a], plateau 1/b on [a, b], ramp down on [b, a + b].  With
-// m = min(u, a) and n = min(a + b - u, a),
-//   F = (m^2/(2a) + (clamp(u, a, b) - a) + (a^2 - n^2)/(2a)) / b,
-// written so that nothing divides by a small width.
-__device__ inline float trap_F(float u, const BoxRow& k)
+// F_0, F_1, F_2 at fraction t (valid for either sign of kappa)
+__device__ inline void box_F(float t, const BoxRow& k, float& F0, float& F1, float& F2)
 {
-    u = fminf(fmaxf(u, 0.f), k.ab);
-    const float m = fminf(u, k.a), n = fminf(k.ab - u, k.a);
-    const float cl = fminf(fmaxf(u, k.a), k.b);
-    return k.invb * fmaf((m - n) * (m + n), k.inv2a, cl - k.ha);
+    const float p = fmaxf(k.a - t, 0.f), q = fmaxf(t + k.am1, 0.f);
+    F0 = fmaf(-k.k0 * p, p, 1.f);
+    F2 = (k.k2 * q) * q;
+    F1 = fmaf((p - q) * (p + q), k.k1, fmaf(t, k.invb, k.c1));
+}
+
+// F(t) of a line with kappa >= 0
+__device__ inline float box_F1(float t, const BoxRow& k)
+{
+    const float p = fmaxf(k.a - t, 0.f), q = fmaxf(t + k.am1, 0.f);
+    return fmaf((p - q) * (p + q), k.k1, fmaf(t, k.invb, k.c1));
 }
 
 // ---------------------------------------------------------------- forward
@@ -601,13 +615,13 @@ __device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const
         if constexpr (NEG) {
             float c[4];
             load_run<4>((const float*)(Cb + (off + (i0 - 1u) * 4u)), c);
-            const float u0 = t + bk.ofs;
-            const float F0 = trap_F(u0, bk), F1 = trap_F(u0 - 1.f, bk), F2 = trap_F(u0 - 2.f, bk);
+            float F0, F1, F2;
+            box_F(t, bk, F0, F1, F2);
             part += fmaf(F2, c[3] - c[2], fmaf(F1, c[2] - c[1], fmaf(F0, c[1] - c[0], c[0])));
         } else {
             float c[2];
             load_run<2>((const float*)(Cb + (off + i0 * 4u)), c);
-            part += fmaf(trap_F(t, bk), c[1] - c[0], c[0]);
+            part += fmaf(box_F1(t, bk), c[1] - c[0], c[0]);
         }
         q += kap;
         off += step;
@@ -634,7 +648,7 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
     if constexpr (N == kBox3) {
         // the footprint reaches 1 (kappa >= 0) or 1 + |kappa| minor cells
         int jlo, jhi;
-        row_range(x0, kap, 1.0 + fabs(kap), nmaj, nmin, &jlo, &jhi);
+        row_range(x0, kap, kap >= 0.0 ? 1.0 : 1.0 - kap, nmaj, nmin, &jlo, &jhi);
         ja = max(jlo, strip * kStrip);
         jb = min(jhi, strip * kStrip + kStrip - 1);
         const BoxRow bk = box_row(kap);
@@ -915,14 +929,16 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
         const uint32_t rb = __umul24((uint32_t)(row0 + jj), (uint32_t)W);
         int* ar = s_a + (rb + (uint32_t)((int)fl - 1));
         if constexpr (NEG) {
-            const float u0 = t + bk.ofs;
-            const float F0 = trap_F(u0, bk), F1 = trap_F(u0 - 1.f, bk), F2 = trap_F(u0 - 2.f, bk);
-            atomicAdd(ar, fixed_round(svs, 1.f - F0));
-            atomicAdd(ar + 1, fixed_round(svs, F0 - F1));
+            // kappa < 0: 1 - F_0 = k0 p^2 is formed directly
+            const float p = fmaxf(bk.a - t, 0.f), qq = fmaxf(t + bk.am1, 0.f);
+            const float w0 = (bk.k0 * p) * p, F2 = (bk.k2 * qq) * qq;
+            const float F1 = fmaf(t, bk.invb, bk.c1);
+            atomicAdd(ar, fixed_round(svs, w0));
+            atomicAdd(ar + 1, fixed_round(svs, (1.f - w0) - F1));
             atomicAdd(ar + 2, fixed_round(svs, F1 - F2));
             atomicAdd(ar + 3, fixed_round(svs, F2));
         } else {
-            const float F = trap_F(t, bk);
+            const float F = box_F1(t, bk);
             atomicAdd(ar + 1, fixed_round(svs, 1.f - F));
             atomicAdd(ar + 2, fixed_round(svs, F));
         }
@@ -938,16 +954,20 @@ __device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, f
     const double x0 = xc - kap * jc;
     const int nmin = vert ? A.nx : A.ny;
     int jlo, jhi;
-    row_range(x0, kap, 1.0 + fabs(kap), nmaj, nmin, &jlo, &jhi);
+    // rows whose crossing lies within the footprint's half-width (1 for
+    // kappa >= 0, 1 + |kappa| otherwise; at most marg) of the tile
+    const double ml = kap >= 0.0 ? 1.0 : 1.0 - kap;
+    row_range(x0, kap, ml, nmaj, nmin, &jlo, &jhi);
     int ra = max(jlo, maj0), rb = min(jhi, maj0 + TM - 1);
     if (kap != 0.0) {
-        double a = (min0 - marg - x0) / kap, b = (min0 + TN - 1 + marg - x0) / kap;
+        double a = (min0 - ml - x0) / kap, b = (min0 + TN - 1 + ml - x0) / kap;
         double lo2 = fmin(a, b), hi2 = fmax(a, b);
         ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
         rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
-    } else if (!(x0 >= min0 - marg && x0 <= min0 + TN - 1 + marg)) {
+    } else if (!(x0 >= min0 - ml && x0 <= min0 + TN - 1 + ml)) {
         return;
     }
+    (void)marg;
     if (ra > rb) return;
     const BoxRow bk = box_row(kap);
     const double q0 = x0 + kap * (double)ra - (double)min0 + (double)kHalo;
