@@ -778,6 +778,7 @@ struct AdjArgs {
     int split;     // workgroups per tile (blockIdx.y): chunk c goes to workgroup c % split
     float* part;   // [split][ny][nx] partial images when split > 1
     float* out;
+    int accumulate;  // 1: out += this launch's image (the second pass of a plan's adjoint)
 };
 
 // accumulator rows are padded to an odd pitch so that the rows the lanes of a
@@ -1048,12 +1049,26 @@ struct AdjShared {
     float red[4];
 };
 
-// One pixel tile of the adjoint (both orientations); `kpart` selects this
-// workgroup's share of the candidate chunks when A.split > 1.  The table
-// must already be in sh.tab.
-template <int N>
+// Which lines a tile takes: both orientations on a kTileI x kTileJ tile (one
+// workgroup writes the tile once: the batched adjoint), the vertical lines
+// on that tile, or the horizontal lines on the transposed kTileJ x kTileI
+// tile.  A tile is always long (kTileI) across the lines it takes, so a line
+// rarely leaves its rows early; the two single-orientation launches of a
+// plan's adjoint add into one image.
+enum AdjMode { kAdjBoth = 0, kAdjVert = 1, kAdjHoriz = 2 };
+
+template <int MODE>
+__device__ constexpr int adj_ti() { return MODE == kAdjHoriz ? kTileJ : kTileI; }
+template <int MODE>
+__device__ constexpr int adj_tj() { return MODE == kAdjHoriz ? kTileI : kTileJ; }
+
+// One pixel tile of the adjoint; `kpart` selects this workgroup's share of
+// the candidate chunks when A.split > 1.  The table must already be in
+// sh.tab.
+template <int N, int MODE>
 __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, AdjShared& sh)
 {
+    constexpr int TI = adj_ti<MODE>(), TJ = adj_tj<MODE>();
     int* s_a = sh.a;
     int* s_k = sh.k;
     const float4* s_tab = sh.tab;
@@ -1063,7 +1078,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
     float* s_red = sh.red;
     const int tid = threadIdx.x;
     const int ti = tile % A.tiles_i, tj = tile / A.tiles_i;
-    const int i0 = ti * kTileI, j0 = tj * kTileJ;
+    const int i0 = ti * TI, j0 = tj * TJ;
     // a row whose crossing X lies outside (min0 - (n+1), min0 + TN + n) adds
     // nothing to the tile's outputs: its taps J-d (J = floor(X + (n+1)/2))
     // miss [min0, min0 + TN) and its knots (within (n+1)/2 of X + (n+1)/2)
@@ -1074,11 +1089,11 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 #pragma unroll
     for (int e = 0; e < kPix; ++e) o[e] = 0.f;
 
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = MODE == kAdjHoriz ? 1 : 0; pass < (MODE == kAdjVert ? 1 : 2); ++pass) {
         const bool vert = pass == 0;
         // tile in (major, minor) coordinates of this orientation
         const int maj0 = vert ? j0 : i0, min0 = vert ? i0 : j0;
-        const int TM = vert ? kTileJ : kTileI, TN = vert ? kTileI : kTileJ;
+        const int TM = vert ? TJ : TI, TN = vert ? TI : TJ;
         const int nmaj = vert ? A.ny : A.nx;
         const int W = TN + 2 * kHalo + 1;  // odd pitch
         const int nbk = vert ? A.nbk_v : A.nbk_h;
@@ -1160,7 +1175,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 #pragma unroll
             for (int q = 0; q < kPix; ++q) {
                 const int p = tid + q * kBlock;
-                const int pj = p / kTileI, pi = p % kTileI;  // pixel (row, column) in the tile
+                const int pj = p / TI, pi = p % TI;  // pixel (row, column) in the tile
                 const int lmaj = vert ? pj : pi, lmin = vert ? pi : pj;
                 const int* ar = s_a + lmaj * W + kHalo + lmin;
                 if constexpr (N == kBox3) {
@@ -1185,16 +1200,17 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 #pragma unroll
     for (int e = 0; e < kPix; ++e) {
         const int p = tid + e * kBlock;
-        const int pj = p / kTileI, pi = p % kTileI;
+        const int pj = p / TI, pi = p % TI;
         const int i = i0 + pi, j = j0 + pj;
         if (i < A.nx && j < A.ny) {
             if (A.split > 1) A.part[((int64_t)kpart * A.ny + j) * A.nx + i] = o[e];
+            else if (A.accumulate) A.out[(int64_t)j * A.nx + i] += o[e];
             else A.out[(int64_t)j * A.nx + i] = o[e];
         }
     }
 }
 
-template <int N>
+template <int N, int MODE>
 __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
 {
     __shared__ AdjShared sh;
@@ -1204,16 +1220,18 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
     }
     const int tile = xcd_logical(blockIdx.x, A.ntiles_pad);
     if (tile >= A.ntiles) return;  // uniform per block
-    adj_tile<N>(A, tile, (int)blockIdx.y, sh);
+    adj_tile<N, MODE>(A, tile, (int)blockIdx.y, sh);
 }
 
-// out = sum over the split workgroups' partial images, in a fixed order
-__global__ void __launch_bounds__(kBlock) k_adj_reduce(const float* part, int split, int64_t npix, float* out)
+// out (+)= sum over the split workgroups' partial images, in a fixed order
+__global__ void __launch_bounds__(kBlock) k_adj_reduce(const float* part, int split, int64_t npix, int accumulate,
+                                                       float* out)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= npix) return;
     float v = part[k];
     for (int g = 1; g < split; ++g) v += part[(int64_t)g * npix + k];
+    if (accumulate) v += out[k];
     out[k] = v;
 }
 
@@ -1340,11 +1358,11 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs
             __syncthreads();
         }
         switch (deg) {
-        case 0: adj_tile<0>(P.a, w.y, 0, sh); break;
-        case 1: adj_tile<1>(P.a, w.y, 0, sh); break;
-        case 2: adj_tile<2>(P.a, w.y, 0, sh); break;
-        case 3: adj_tile<3>(P.a, w.y, 0, sh); break;
-        default: adj_tile<kBox3>(P.a, w.y, 0, sh); break;
+        case 0: adj_tile<0, kAdjBoth>(P.a, w.y, 0, sh); break;
+        case 1: adj_tile<1, kAdjBoth>(P.a, w.y, 0, sh); break;
+        case 2: adj_tile<2, kAdjBoth>(P.a, w.y, 0, sh); break;
+        case 3: adj_tile<3, kAdjBoth>(P.a, w.y, 0, sh); break;
+        default: adj_tile<kBox3, kAdjBoth>(P.a, w.y, 0, sh); break;
         }
     }
 }
@@ -1497,8 +1515,9 @@ static FwdArgs make_fwd_args(const xrt_plan* p, float* sino)
     return a;
 }
 
-static AdjArgs make_adj_args(const xrt_plan* p, float* out)
+static AdjArgs make_adj_args(const xrt_plan* p, float* out, int mode = kAdjBoth)
 {
+    const int ti = mode == kAdjHoriz ? kTileJ : kTileI, tj = mode == kAdjHoriz ? kTileI : kTileJ;
     AdjArgs a;
     a.xc = p->xc;
     a.kap = p->kap;
@@ -1511,13 +1530,14 @@ static AdjArgs make_adj_args(const xrt_plan* p, float* out)
     a.nbk_h = p->nbk_h;
     a.boff_v = p->boff_v;
     a.boff_h = p->boff_h;
-    a.tiles_i = (p->g.nx + kTileI - 1) / kTileI;
-    a.tiles_j = (p->g.ny + kTileJ - 1) / kTileJ;
+    a.tiles_i = (p->g.nx + ti - 1) / ti;
+    a.tiles_j = (p->g.ny + tj - 1) / tj;
     a.ntiles = a.tiles_i * a.tiles_j;
     a.ntiles_pad = (a.ntiles + 7) / 8 * 8;
     a.out = out;
     a.split = 1;
     a.part = nullptr;
+    a.accumulate = 0;
     return a;
 }
 
@@ -1576,19 +1596,31 @@ hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, h
     return e;
 }
 
-template <int N>
-static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
+// The vertical lines on kTileI x kTileJ tiles write the image; the
+// horizontal lines on the transposed tiles then add to it (same stream, so
+// the second launch sees the first's writes).
+template <int N, int MODE>
+static hipError_t adjoint_pass(const xrt_plan* p, float* out, hipStream_t s)
 {
-    AdjArgs a = make_adj_args(p, out);
+    AdjArgs a = make_adj_args(p, out, MODE);
     a.split = p->adj_split;
     a.part = p->adj_part;
-    hipLaunchKernelGGL(k_adjoint<N>, dim3((unsigned)a.ntiles_pad, (unsigned)a.split), dim3(kBlock), 0, s, a);
+    a.accumulate = MODE == kAdjHoriz ? 1 : 0;
+    hipLaunchKernelGGL((k_adjoint<N, MODE>), dim3((unsigned)a.ntiles_pad, (unsigned)a.split), dim3(kBlock), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.split == 1) return e;
     const int64_t npix = (int64_t)p->g.nx * p->g.ny;
     hipLaunchKernelGGL(k_adj_reduce, dim3((unsigned)((npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.part,
-                       a.split, npix, out);
+                       a.split, npix, a.accumulate, out);
     return hipGetLastError();
+}
+
+template <int N>
+static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
+{
+    hipError_t e = adjoint_pass<N, kAdjVert>(p, out, s);
+    if (e != hipSuccess) return e;
+    return adjoint_pass<N, kAdjHoriz>(p, out, s);
 }
 
 static hipError_t sort_sino(const xrt_plan* p, const float* sino, hipStream_t s)
