@@ -1038,16 +1038,26 @@ __device__ inline float block_max(float v, float* red)
 #define XRT_ADJ_WAVES 4
 #endif
 #define XRT_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(XRT_ADJ_WAVES, XRT_ADJ_WAVES)))
-// LDS of one adjoint workgroup
-struct AdjShared {
-    int a[kAccWords];
-    int k[kAccWords];
+// single-orientation launches (smaller accumulators, fewer registers)
+#ifndef XRT_ADJ1_WAVES
+#define XRT_ADJ1_WAVES 5
+#endif
+#define XRT_ADJ1_ATTR __attribute__((amdgpu_waves_per_eu(XRT_ADJ1_WAVES, XRT_ADJ1_WAVES)))
+// LDS of one adjoint workgroup; W words per accumulator
+template <int W>
+struct AdjSharedT {
+    int a[W];
+    int k[W];
     float4 tab[kTabMax];
     uint32_t start[kSlopeBins];
     uint32_t pre[kSlopeBins + 1];
     uint32_t scan[kBlock];
     float red[4];
 };
+using AdjShared = AdjSharedT<kAccWords>;
+// a single orientation: kTileJ major rows of kTileI (+ halos) minor words
+constexpr int kAccWords1 = kTileJ * (kTileI + 2 * kHalo + 1);
+using AdjShared1 = AdjSharedT<kAccWords1>;
 
 // Which lines a tile takes: both orientations on a kTileI x kTileJ tile (one
 // workgroup writes the tile once: the batched adjoint), the vertical lines
@@ -1065,8 +1075,8 @@ __device__ constexpr int adj_tj() { return MODE == kAdjHoriz ? kTileI : kTileJ; 
 // One pixel tile of the adjoint; `kpart` selects this workgroup's share of
 // the candidate chunks when A.split > 1.  The table must already be in
 // sh.tab.
-template <int N, int MODE>
-__device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, AdjShared& sh)
+template <int N, int MODE, class SH>
+__device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, SH& sh)
 {
     constexpr int TI = adj_ti<MODE>(), TJ = adj_tj<MODE>();
     int* s_a = sh.a;
@@ -1211,9 +1221,10 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 }
 
 template <int N, int MODE>
-__global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
+__global__ void __launch_bounds__(kBlock) XRT_ADJ1_ATTR k_adjoint(AdjArgs A)
 {
-    __shared__ AdjShared sh;
+    static_assert(MODE != kAdjBoth, "a plan's adjoint takes one orientation per launch");
+    __shared__ AdjShared1 sh;
     if constexpr (N != kBox3) {
         const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
         for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
