@@ -1087,7 +1087,12 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
     uint32_t* s_scan = sh.scan;
     float* s_red = sh.red;
     const int tid = threadIdx.x;
-    const int ti = tile % A.tiles_i, tj = tile / A.tiles_i;
+    // consecutive tiles (one XCD's range, sharing its L2) run along the
+    // lines: down a column of tiles for vertical lines, along a row for
+    // horizontal ones (and for tiles that take both)
+    constexpr bool kColMajor = MODE == kAdjVert;
+    const int ti = kColMajor ? tile / A.tiles_j : tile % A.tiles_i;
+    const int tj = kColMajor ? tile % A.tiles_j : tile / A.tiles_i;
     const int i0 = ti * TI, j0 = tj * TJ;
     // a row whose crossing X lies outside (min0 - (n+1), min0 + TN + n) adds
     // nothing to the tile's outputs: its taps J-d (J = floor(X + (n+1)/2))
