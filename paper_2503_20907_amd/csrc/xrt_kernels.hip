@@ -364,9 +364,10 @@ template <int N, int S>
 __device__ inline void row_core(double q, const LineConst& k, const float4* __restrict__ tab,
                                 Row<S>& R)
 {
-    const double Jd = floor(q);
-    const float t = (float)(q - Jd);
-    R.J = (int)Jd;
+    // q > 0 here (a padded or halo-relative column coordinate), so truncation
+    // is the floor
+    const float t = (float)__builtin_amdgcn_fract(q);
+    R.J = (int)q;
     R.t = t;
     // the S knots nearest to q: centred on round(q) for odd S, on q for even S
     int o;
@@ -566,7 +567,8 @@ struct FwdArgs {
 
 // Sum over the rows [ja, jb] of one line (times tap_scale<N>).  C and D are
 // the layout bases (uniform); element (row j, minor i) sits at
-// j * pitch + kPad + i.
+// j * pitch + kPad + i, and q is X + (n+1)/2 + kPad at row ja (the padded
+// column coordinate, positive on every row a line reaches).
 template <int N, int S>
 __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const LineConst& lc,
                                  const float4* __restrict__ tab, const float* __restrict__ C,
@@ -578,7 +580,7 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     // uniform base plus a 32-bit offset
     const char* __restrict__ Cb = (const char*)C;
     const char* __restrict__ Db = (const char*)D;
-    uint32_t off = ((uint32_t)ja * (uint32_t)pitch + kPad) * 4u;
+    uint32_t off = (uint32_t)ja * (uint32_t)pitch * 4u;
     const uint32_t step = (uint32_t)pitch * 4u;
     float part = 0.f;
     for (int j = ja; j <= jb; ++j) {
@@ -604,14 +606,14 @@ template <bool NEG>
 __device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const BoxRow& bk,
                                      const float* __restrict__ C, int pitch)
 {
+    // q = X + kPad at row ja (padded column coordinate, positive)
     const char* __restrict__ Cb = (const char*)C;
-    uint32_t off = ((uint32_t)ja * (uint32_t)pitch + kPad) * 4u;
+    uint32_t off = (uint32_t)ja * (uint32_t)pitch * 4u;
     const uint32_t step = (uint32_t)pitch * 4u;
     float part = 0.f;
     for (int j = ja; j <= jb; ++j) {
-        const double fl = floor(q);
-        const float t = (float)(q - fl);
-        const uint32_t i0 = (uint32_t)(int)fl;
+        const float t = (float)__builtin_amdgcn_fract(q);
+        const uint32_t i0 = (uint32_t)(int)q;
         if constexpr (NEG) {
             float c[4];
             load_run<4>((const float*)(Cb + (off + (i0 - 1u) * 4u)), c);
@@ -654,7 +656,7 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
         const BoxRow bk = box_row(kap);
         const bool neg = __ballot(ja <= jb && bk.neg) != 0ull;
         if (ja <= jb) {
-            const double q0 = x0 + kap * (double)ja;
+            const double q0 = x0 + kap * (double)ja + (double)kPad;
             acc = neg ? fwd_walk_box<true>(q0, kap, ja, jb, bk, C, pitch)
                       : fwd_walk_box<false>(q0, kap, ja, jb, bk, C, pitch);
         }
@@ -667,7 +669,7 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
         const LineConst lc = line_const<N>(kap);
         const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
         if (ja <= jb) {
-            const double q0 = x0 + kap * (double)ja + H;
+            const double q0 = x0 + kap * (double)ja + H + (double)kPad;
             if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
             else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
             else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
@@ -924,11 +926,11 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
 {
     int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
     for (int c = 0; c < cnt; ++c) {
+        // q > 0 (halo-relative column), so truncation is the floor
         const double q = fma(kap, (double)jj, q0);
-        const double fl = floor(q);
-        const float t = (float)(q - fl);
+        const float t = (float)__builtin_amdgcn_fract(q);
         const uint32_t rb = __umul24((uint32_t)(row0 + jj), (uint32_t)W);
-        int* ar = s_a + (rb + (uint32_t)((int)fl - 1));
+        int* ar = s_a + (rb + (uint32_t)((int)q - 1));
         if constexpr (NEG) {
             // kappa < 0: 1 - F_0 = k0 p^2 is formed directly
             const float p = fmaxf(bk.a - t, 0.f), qq = fmaxf(t + bk.am1, 0.f);
