@@ -17,9 +17,10 @@ constexpr int kSlopeBins = 512;
 constexpr int kTabPerUnit = 64;
 // Largest table: degree 3, half-support 2 -> 128 intervals + 1 zero interval.
 constexpr int kTabMax = kTabPerUnit * 2 + 1;
-// Adjoint tile (pixels): kTileI columns (x1) by kTileJ rows (x2).  64 x 32
-// (32 KB of LDS, <= 128 VGPRs, 4 waves per SIMD) measured fastest among
-// 32..128-wide tiles on the 2048^2 cubic workload.
+// Adjoint tile (pixels): kTileI columns (x1) by kTileJ rows (x2) for the
+// vertical lines, and the transposed tile for the horizontal ones (kTileI
+// across the lines either way).  64 x 32 measured fastest among 16..128-pixel
+// tile sides on the 2048^2 cubic workload.
 #ifndef XRT_TILE_I
 #define XRT_TILE_I 64
 #endif

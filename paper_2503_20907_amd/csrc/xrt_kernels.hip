@@ -1035,12 +1035,13 @@ __device__ inline float block_max(float v, float* red)
     return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
-// 4 waves per SIMD: the register budget that matches the LDS of a 64 x 32 tile
+// Waves per SIMD.  Tiles that take both orientations (the batched adjoint):
+// 4, the register budget that matches their LDS
 #ifndef XRT_ADJ_WAVES
 #define XRT_ADJ_WAVES 4
 #endif
 #define XRT_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(XRT_ADJ_WAVES, XRT_ADJ_WAVES)))
-// single-orientation launches (smaller accumulators, fewer registers)
+// single-orientation launches (smaller accumulators, fewer registers): 5
 #ifndef XRT_ADJ1_WAVES
 #define XRT_ADJ1_WAVES 5
 #endif
