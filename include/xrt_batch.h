@@ -15,13 +15,17 @@
  * Work is split into items: (problem, strip of 128 grid rows, block of lines)
  * for the forward -- a problem's items strip by strip, so the workgroups in
  * flight share one strip of its coefficient layouts -- and (problem, pixel
- * tile) for the adjoint, listed largest problem first.  A
- * fixed grid of workgroups (blocks_per_cu per compute unit) takes items from
- * one atomic counter until the list is exhausted; each item is computed by
- * one workgroup and written once (the adjoint stays a gather).  Results are
- * identical for every configuration: a line's per-strip sum (summed over
- * strips in a fixed order) or a tile's gather never depends on which
- * workgroup runs it.
+ * tile) for the adjoint, listed largest problem first.  The adjoint takes
+ * two persistent launches: the lines closer to vertical on 64 x 32 tiles,
+ * which write the images, then the lines closer to horizontal on 32 x 64
+ * tiles, which add into them (a tile is 64 pixels across the lines it
+ * takes).  A fixed grid of workgroups (blocks_per_cu per compute unit) takes
+ * items from one atomic counter per launch until the list is exhausted; each
+ * item is computed by one workgroup, which alone writes its pixels in that
+ * launch (the adjoint stays a gather, with no atomics on the images).
+ * Results are identical for every configuration: a line's per-strip sum
+ * (summed over strips in a fixed order) or a tile's gather never depends on
+ * which workgroup runs it.
  *
  * Conventions are those of xrt.h (status codes, streams, xrt_last_error).
  */
@@ -66,7 +70,7 @@ xrt_status xrt_batch_buffers(const xrt_batch* b, int32_t p, float** coeffs, floa
 xrt_status xrt_batch_info(const xrt_batch* b, int64_t* total_lines, int32_t* fwd_items, int32_t* adj_items);
 
 /* sino_p = H_p coeffs_p for every p (one persistent launch after the
- * per-problem layout passes); back_p = H_p^T sino_p (one persistent launch
+ * per-problem layout passes); back_p = H_p^T sino_p (two persistent launches
  * after the per-problem sinogram reordering).  No synchronisation, no
  * allocation.  Errors: EINVAL, EHIP. */
 xrt_status xrt_batch_forward(xrt_batch* b, void* stream);

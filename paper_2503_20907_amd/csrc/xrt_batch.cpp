@@ -29,9 +29,10 @@ struct xrt_batch {
     float* spart = nullptr;                   // per-strip forward partial sums of all problems
     void* probs = nullptr;                    // device table of launch records
     int2* items_f = nullptr;
-    int2* items_a = nullptr;
-    int nitems_f = 0, nitems_a = 0;
-    unsigned int* counters = nullptr;         // [0] forward, [1] adjoint
+    int2* items_a = nullptr;                  // adjoint, vertical lines
+    int2* items_ah = nullptr;                 // adjoint, horizontal lines
+    int nitems_f = 0, nitems_a = 0, nitems_ah = 0;
+    unsigned int* counters = nullptr;         // [0] forward, [1] adjoint vertical, [2] adjoint horizontal
     int64_t total_lines = 0;
     int cus = 0;
     xrt_batch_config cfg;
@@ -67,9 +68,12 @@ bool config_ok(const xrt_batch_config& c)
            c.adj_blocks_per_cu <= 32;
 }
 
-int tiles_of(const xrt_plan* p)
+// adjoint tiles of a plan: kTileI x kTileJ for the vertical lines, the
+// transposed kTileJ x kTileI for the horizontal ones
+int tiles_of(const xrt_plan* p, bool horizontal = false)
 {
-    return ((p->g.nx + xrt::kTileI - 1) / xrt::kTileI) * ((p->g.ny + xrt::kTileJ - 1) / xrt::kTileJ);
+    const int ti = horizontal ? xrt::kTileJ : xrt::kTileI, tj = horizontal ? xrt::kTileI : xrt::kTileJ;
+    return ((p->g.nx + ti - 1) / ti) * ((p->g.ny + tj - 1) / tj);
 }
 
 // forward list: every block of lines of every problem, largest problem first
@@ -92,15 +96,20 @@ xrt_status build_forward_items(xrt_batch* b)
     return XRT_OK;
 }
 
+// adjoint lists: every tile of every problem, largest problem first, one
+// list per orientation
 xrt_status build_adjoint_items(xrt_batch* b)
 {
-    std::vector<int2> it;
-    for (int p : b->order_a)
-        for (int t = 0; t < tiles_of(b->plans[p]); ++t) it.push_back(make_int2(p, t));
-    b->nitems_a = (int)it.size();
-    XB_CHECK(hipMalloc((void**)&b->items_a, std::max<size_t>(1, it.size()) * sizeof(int2)), "hipMalloc");
-    if (!it.empty())
-        XB_CHECK(hipMemcpy(b->items_a, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice), "hipMemcpy");
+    for (int h = 0; h < 2; ++h) {
+        std::vector<int2> it;
+        for (int p : b->order_a)
+            for (int t = 0; t < tiles_of(b->plans[p], h == 1); ++t) it.push_back(make_int2(p, t));
+        int2** dst = h ? &b->items_ah : &b->items_a;
+        (h ? b->nitems_ah : b->nitems_a) = (int)it.size();
+        XB_CHECK(hipMalloc((void**)dst, std::max<size_t>(1, it.size()) * sizeof(int2)), "hipMalloc");
+        if (!it.empty())
+            XB_CHECK(hipMemcpy(*dst, it.data(), it.size() * sizeof(int2), hipMemcpyHostToDevice), "hipMemcpy");
+    }
     return XRT_OK;
 }
 
@@ -109,7 +118,7 @@ void release(xrt_batch* b)
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     for (xrt_plan* p : b->plans) xrt_plan_destroy(p);
-    void* ptrs[] = {b->buf, b->spart, b->probs, b->items_f, b->items_a, b->counters};
+    void* ptrs[] = {b->buf, b->spart, b->probs, b->items_f, b->items_a, b->items_ah, b->counters};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     b->magic = 0;
@@ -121,7 +130,7 @@ hipError_t enqueue_forward(xrt_batch* b, hipStream_t s)
         hipError_t e = xrt::launch_layouts(b->plans[p], b->coeffs[p], s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = xrt::launch_reset_counters(b->counters, 2, s);
+    hipError_t e = xrt::launch_reset_counters(b->counters, 3, s);
     if (e == hipSuccess && b->nitems_f > 0)
         e = xrt::launch_batch_forward(b->probs, b->items_f, b->nitems_f, b->counters, b->cfg.lines_per_item,
                                       b->cus * b->cfg.fwd_blocks_per_cu, s);
@@ -136,10 +145,14 @@ hipError_t enqueue_adjoint(xrt_batch* b, hipStream_t s)
         hipError_t e = xrt::launch_sort_sino(b->plans[p], b->sino[p], s);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = xrt::launch_reset_counters(b->counters, 2, s);
+    hipError_t e = xrt::launch_reset_counters(b->counters, 3, s);
     if (e != hipSuccess || b->nitems_a == 0) return e;
-    return xrt::launch_batch_adjoint(b->probs, b->items_a, b->nitems_a, b->counters + 1,
-                                     b->cus * b->cfg.adj_blocks_per_cu, s);
+    // the horizontal lines add into the images the vertical launch wrote
+    e = xrt::launch_batch_adjoint(b->probs, b->items_a, b->nitems_a, b->counters + 1,
+                                  b->cus * b->cfg.adj_blocks_per_cu, 0, s);
+    if (e != hipSuccess) return e;
+    return xrt::launch_batch_adjoint(b->probs, b->items_ah, b->nitems_ah, b->counters + 2,
+                                     b->cus * b->cfg.adj_blocks_per_cu, 1, s);
 }
 
 void drop_graph(xrt_batch* b)
@@ -195,7 +208,7 @@ xrt_status xrt_batch_create(const xrt_problem* problems, int32_t count, void* st
     hipError_t e = hipMalloc((void**)&b->buf, total * sizeof(float));
     if (e == hipSuccess) e = hipMemsetAsync(b->buf, 0, total * sizeof(float), s);
     if (e == hipSuccess) e = hipMalloc((void**)&b->spart, std::max<int64_t>(spart_total, 1) * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->counters, 2 * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->counters, 3 * sizeof(unsigned int));
     if (e == hipSuccess) e = hipMalloc(&b->probs, (size_t)count * xrt::batch_prob_size());
     if (e != hipSuccess) {
         xrt_status st = e == hipErrorOutOfMemory ? XRT_ENOMEM : hip_fail("xrt_batch_create", e);
@@ -264,7 +277,7 @@ xrt_status xrt_batch_info(const xrt_batch* b, int64_t* total_lines, int32_t* fwd
     if (!batch_ok(b)) return XRT_EINVAL;
     if (total_lines) *total_lines = b->total_lines;
     if (fwd_items) *fwd_items = b->nitems_f;
-    if (adj_items) *adj_items = b->nitems_a;
+    if (adj_items) *adj_items = b->nitems_a + b->nitems_ah;
     return XRT_OK;
 }
 

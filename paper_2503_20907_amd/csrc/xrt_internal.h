@@ -97,7 +97,7 @@ hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, h
 hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s);
 hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s);
 
-// batches of plans (one persistent launch per direction; see xrt_batch.cpp)
+// batches of plans (persistent launches; see xrt_batch.cpp)
 size_t batch_prob_size();
 // strips of the forward schedule of a plan (per-strip partial sums: strips x lines floats)
 int batch_strips(const xrt_plan* p);
@@ -109,8 +109,10 @@ hipError_t launch_sort_sino(const xrt_plan* p, const float* sino, hipStream_t s)
 hipError_t launch_reset_counters(unsigned int* c, int n, hipStream_t s);
 hipError_t launch_batch_forward(const void* probs, const int2* items, int nitems, unsigned int* counter,
                                 int lines_per_item, int grid, hipStream_t s);
+// horizontal = 0: the vertical lines on kTileI x kTileJ tiles (writes the
+// images); 1: the horizontal lines on the transposed tiles (adds into them)
 hipError_t launch_batch_adjoint(const void* probs, const int2* items, int nitems, unsigned int* counter, int grid,
-                                hipStream_t s);
+                                int horizontal, hipStream_t s);
 // Knot-transition table of degree n (host, FP64-built, rounded to float):
 // kTabPerUnit*(n+1)/2 cubic intervals plus one zero interval, 4 floats each.
 const float* etable_host(int n, int* n_entries);

@@ -784,12 +784,10 @@ struct AdjArgs {
 };
 
 // accumulator rows are padded to an odd pitch so that the rows the lanes of a
-// wave update fall into different LDS banks
-// words per accumulator: the vertical pass holds kTileJ rows of the tile's
-// columns, the horizontal pass kTileI rows of its rows (each with halos)
-constexpr int kAccWords = (kTileJ * (kTileI + 2 * kHalo + 1) > kTileI * (kTileJ + 2 * kHalo + 1))
-                              ? kTileJ * (kTileI + 2 * kHalo + 1)
-                              : kTileI * (kTileJ + 2 * kHalo + 1);
+// wave update fall into different LDS banks; an accumulator holds the
+// tile's kTileJ rows along the lines, each kTileI wide across them, plus
+// halos
+constexpr int kAccWords = kTileJ * (kTileI + 2 * kHalo + 1);
 constexpr int kPix = kTileI * kTileJ / kBlock;
 
 // The LDS accumulators are int32 fixed point: float atomic adds to LDS are an
@@ -1035,40 +1033,28 @@ __device__ inline float block_max(float v, float* red)
     return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
-// Waves per SIMD.  Tiles that take both orientations (the batched adjoint):
-// 4, the register budget that matches their LDS
+// 5 waves per SIMD (95 VGPRs, 29 KB of LDS per workgroup)
 #ifndef XRT_ADJ_WAVES
-#define XRT_ADJ_WAVES 4
+#define XRT_ADJ_WAVES 5
 #endif
 #define XRT_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(XRT_ADJ_WAVES, XRT_ADJ_WAVES)))
-// single-orientation launches (smaller accumulators, fewer registers): 5
-#ifndef XRT_ADJ1_WAVES
-#define XRT_ADJ1_WAVES 5
-#endif
-#define XRT_ADJ1_ATTR __attribute__((amdgpu_waves_per_eu(XRT_ADJ1_WAVES, XRT_ADJ1_WAVES)))
-// LDS of one adjoint workgroup; W words per accumulator
-template <int W>
-struct AdjSharedT {
-    int a[W];
-    int k[W];
+// LDS of one adjoint workgroup
+struct AdjShared {
+    int a[kAccWords];
+    int k[kAccWords];
     float4 tab[kTabMax];
     uint32_t start[kSlopeBins];
     uint32_t pre[kSlopeBins + 1];
     uint32_t scan[kBlock];
     float red[4];
 };
-using AdjShared = AdjSharedT<kAccWords>;
-// a single orientation: kTileJ major rows of kTileI (+ halos) minor words
-constexpr int kAccWords1 = kTileJ * (kTileI + 2 * kHalo + 1);
-using AdjShared1 = AdjSharedT<kAccWords1>;
 
-// Which lines a tile takes: both orientations on a kTileI x kTileJ tile (one
-// workgroup writes the tile once: the batched adjoint), the vertical lines
-// on that tile, or the horizontal lines on the transposed kTileJ x kTileI
-// tile.  A tile is always long (kTileI) across the lines it takes, so a line
-// rarely leaves its rows early; the two single-orientation launches of a
-// plan's adjoint add into one image.
-enum AdjMode { kAdjBoth = 0, kAdjVert = 1, kAdjHoriz = 2 };
+// Which lines a launch takes: the vertical lines on kTileI x kTileJ tiles,
+// or the horizontal lines on the transposed kTileJ x kTileI tiles (adding
+// into the image the first launch wrote).  A tile is thus always kTileI
+// pixels across the lines it takes, so a line rarely leaves the tile's rows
+// early and idles its lane for the rest of the wave's walk.
+enum AdjMode { kAdjVert = 1, kAdjHoriz = 2 };
 
 template <int MODE>
 __device__ constexpr int adj_ti() { return MODE == kAdjHoriz ? kTileJ : kTileI; }
@@ -1078,8 +1064,8 @@ __device__ constexpr int adj_tj() { return MODE == kAdjHoriz ? kTileI : kTileJ; 
 // One pixel tile of the adjoint; `kpart` selects this workgroup's share of
 // the candidate chunks when A.split > 1.  The table must already be in
 // sh.tab.
-template <int N, int MODE, class SH>
-__device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, SH& sh)
+template <int N, int MODE>
+__device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, AdjShared& sh)
 {
     constexpr int TI = adj_ti<MODE>(), TJ = adj_tj<MODE>();
     int* s_a = sh.a;
@@ -1092,7 +1078,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
     const int tid = threadIdx.x;
     // consecutive tiles (one XCD's range, sharing its L2) run along the
     // lines: down a column of tiles for vertical lines, along a row for
-    // horizontal ones (and for tiles that take both)
+    // horizontal ones
     constexpr bool kColMajor = MODE == kAdjVert;
     const int ti = kColMajor ? tile / A.tiles_j : tile % A.tiles_i;
     const int tj = kColMajor ? tile % A.tiles_j : tile / A.tiles_i;
@@ -1107,8 +1093,8 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 #pragma unroll
     for (int e = 0; e < kPix; ++e) o[e] = 0.f;
 
-    for (int pass = MODE == kAdjHoriz ? 1 : 0; pass < (MODE == kAdjVert ? 1 : 2); ++pass) {
-        const bool vert = pass == 0;
+    {
+        constexpr bool vert = MODE == kAdjVert;
         // tile in (major, minor) coordinates of this orientation
         const int maj0 = vert ? j0 : i0, min0 = vert ? i0 : j0;
         const int TM = vert ? TJ : TI, TN = vert ? TI : TJ;
@@ -1229,10 +1215,9 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 }
 
 template <int N, int MODE>
-__global__ void __launch_bounds__(kBlock) XRT_ADJ1_ATTR k_adjoint(AdjArgs A)
+__global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
 {
-    static_assert(MODE != kAdjBoth, "a plan's adjoint takes one orientation per launch");
-    __shared__ AdjShared1 sh;
+    __shared__ AdjShared sh;
     if constexpr (N != kBox3) {
         const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
         for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
@@ -1257,7 +1242,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_reduce(const float* part, int sp
 // ---------------------------------------------------------------- batch
 struct BatchProb {
     FwdArgs f;      // forward of this problem (sino = its sinogram buffer)
-    AdjArgs a;      // adjoint of this problem (split 1, out = its image buffer)
+    AdjArgs a;      // adjoint, vertical lines (split 1, out = its image buffer)
+    AdjArgs ah;     // adjoint, horizontal lines on transposed tiles (adds into out)
     int degree;
     int nstrip;     // strips of kStrip rows (the larger of the two orientations)
     int64_t m_vert, m_valid;
@@ -1359,6 +1345,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_fwd_reduce(const BatchProb* pr
     P.f.sino[P.f.idx[k]] = v;
 }
 
+// One orientation of the adjoint of every problem: the vertical lines on
+// kTileI x kTileJ tiles, or (a second launch, adding into the images) the
+// horizontal lines on the transposed tiles.
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs B)
 {
     __shared__ AdjShared sh;
@@ -1369,19 +1359,20 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs
         if (it >= B.nitems) break;
         const int2 w = B.items[it];
         const BatchProb& P = B.probs[w.x];
+        const AdjArgs& A = MODE == kAdjVert ? P.a : P.ah;
         const int deg = P.degree;
         if (deg != cur) {
             const int ntab = deg == kBox3 ? 0 : kTabPerUnit * (deg + 1) / 2 + 1;
-            for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = P.a.tab[e];
+            for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
             cur = deg;
             __syncthreads();
         }
         switch (deg) {
-        case 0: adj_tile<0, kAdjBoth>(P.a, w.y, 0, sh); break;
-        case 1: adj_tile<1, kAdjBoth>(P.a, w.y, 0, sh); break;
-        case 2: adj_tile<2, kAdjBoth>(P.a, w.y, 0, sh); break;
-        case 3: adj_tile<3, kAdjBoth>(P.a, w.y, 0, sh); break;
-        default: adj_tile<kBox3, kAdjBoth>(P.a, w.y, 0, sh); break;
+        case 0: adj_tile<0, MODE>(A, w.y, 0, sh); break;
+        case 1: adj_tile<1, MODE>(A, w.y, 0, sh); break;
+        case 2: adj_tile<2, MODE>(A, w.y, 0, sh); break;
+        case 3: adj_tile<3, MODE>(A, w.y, 0, sh); break;
+        default: adj_tile<kBox3, MODE>(A, w.y, 0, sh); break;
         }
     }
 }
@@ -1534,7 +1525,7 @@ static FwdArgs make_fwd_args(const xrt_plan* p, float* sino)
     return a;
 }
 
-static AdjArgs make_adj_args(const xrt_plan* p, float* out, int mode = kAdjBoth)
+static AdjArgs make_adj_args(const xrt_plan* p, float* out, int mode)
 {
     const int ti = mode == kAdjHoriz ? kTileJ : kTileI, tj = mode == kAdjHoriz ? kTileI : kTileJ;
     AdjArgs a;
@@ -1698,7 +1689,9 @@ void batch_fill(const xrt_plan* p, float* sino, float* back, float* spart, void*
 {
     BatchProb b;
     b.f = make_fwd_args(p, sino);
-    b.a = make_adj_args(p, back);
+    b.a = make_adj_args(p, back, kAdjVert);
+    b.ah = make_adj_args(p, back, kAdjHoriz);
+    b.ah.accumulate = 1;
     b.degree = p->degree;
     b.nstrip = batch_strips(p);
     b.m_vert = p->m_vert;
@@ -1749,7 +1742,7 @@ hipError_t launch_batch_forward(const void* probs, const int2* items, int nitems
 }
 
 hipError_t launch_batch_adjoint(const void* probs, const int2* items, int nitems, unsigned int* counter, int grid,
-                                hipStream_t s)
+                                int horizontal, hipStream_t s)
 {
     BatchArgs b;
     b.probs = static_cast<const BatchProb*>(probs);
@@ -1757,7 +1750,8 @@ hipError_t launch_batch_adjoint(const void* probs, const int2* items, int nitems
     b.nitems = nitems;
     b.counter = counter;
     b.lines_per_item = kBlock;
-    hipLaunchKernelGGL(k_batch_adjoint, dim3((unsigned)grid), dim3(kBlock), 0, s, b);
+    if (horizontal) hipLaunchKernelGGL(k_batch_adjoint<kAdjHoriz>, dim3((unsigned)grid), dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL(k_batch_adjoint<kAdjVert>, dim3((unsigned)grid), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 
