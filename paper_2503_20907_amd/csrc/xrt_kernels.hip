@@ -112,7 +112,9 @@ __device__ inline Canon canonicalize(const LineIn& L, int64_t m, const GridGeom&
 }
 
 // Rows [jlo, jhi] (closed) of a line whose band may reach the grid.
-__device__ inline void row_range(double x0, double kap, double W, int nmaj, int nmin, int* jlo,
+// inv = 1/kap (unused when kap = 0); a product with it instead of a
+// quotient moves the bounds by ~1e-16 relative, far inside the 1e-9 slack
+__device__ inline void row_range(double x0, double kap, double inv, double W, int nmaj, int nmin, int* jlo,
                                  int* jhi)
 {
     if (kap == 0.0) {
@@ -120,7 +122,7 @@ __device__ inline void row_range(double x0, double kap, double W, int nmaj, int 
         *jhi = nmaj - 1;
         return;
     }
-    double a = (-W - x0) / kap, b = (nmin - 1 + W - x0) / kap;
+    double a = (-W - x0) * inv, b = (nmin - 1 + W - x0) * inv;
     double lo = fmin(a, b), hi = fmax(a, b);
     double flo = ceil(lo - 1e-9), fhi = floor(hi + 1e-9);
     *jlo = (int)fmax(0.0, flo);
@@ -650,7 +652,7 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
     if constexpr (N == kBox3) {
         // the footprint reaches 1 (kappa >= 0) or 1 + |kappa| minor cells
         int jlo, jhi;
-        row_range(x0, kap, kap >= 0.0 ? 1.0 : 1.0 - kap, nmaj, nmin, &jlo, &jhi);
+        row_range(x0, kap, 1.0 / kap, kap >= 0.0 ? 1.0 : 1.0 - kap, nmaj, nmin, &jlo, &jhi);
         ja = max(jlo, strip * kStrip);
         jb = min(jhi, strip * kStrip + kStrip - 1);
         const BoxRow bk = box_row(kap);
@@ -663,7 +665,7 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
     } else {
         const double H = 0.5 * (N + 1);
         int jlo, jhi;
-        row_range(x0, kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
+        row_range(x0, kap, 1.0 / kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
         ja = max(jlo, strip * kStrip);
         jb = min(jhi, strip * kStrip + kStrip - 1);
         const LineConst lc = line_const<N>(kap);
@@ -958,10 +960,11 @@ __device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, f
     // rows whose crossing lies within the footprint's half-width (1 for
     // kappa >= 0, 1 + |kappa| otherwise; at most marg) of the tile
     const double ml = kap >= 0.0 ? 1.0 : 1.0 - kap;
-    row_range(x0, kap, ml, nmaj, nmin, &jlo, &jhi);
+    const double inv = 1.0 / kap;
+    row_range(x0, kap, inv, ml, nmaj, nmin, &jlo, &jhi);
     int ra = max(jlo, maj0), rb = min(jhi, maj0 + TM - 1);
     if (kap != 0.0) {
-        double a = (min0 - ml - x0) / kap, b = (min0 + TN - 1 + ml - x0) / kap;
+        double a = (min0 - ml - x0) * inv, b = (min0 + TN - 1 + ml - x0) * inv;
         double lo2 = fmin(a, b), hi2 = fmax(a, b);
         ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
         rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
@@ -994,11 +997,12 @@ __device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float
         // rows whose crossing lies within the footprint's half-width
         // H (1 + |kappa|) of the tile (at most marg)
         const double ml = H * (1.0 + fabs(kap));
-        row_range(x0, kap, ml, nmaj, nmin, &jlo, &jhi);
+        const double inv = 1.0 / kap;
+        row_range(x0, kap, inv, ml, nmaj, nmin, &jlo, &jhi);
         ra = max(jlo, maj0);
         rb = min(jhi, maj0 + TM - 1);
         if (kap != 0.0) {
-            double a = (min0 - ml - x0) / kap, b = (min0 + TN - 1 + ml - x0) / kap;
+            double a = (min0 - ml - x0) * inv, b = (min0 + TN - 1 + ml - x0) * inv;
             double lo2 = fmin(a, b), hi2 = fmax(a, b);
             ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
             rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
@@ -1404,7 +1408,7 @@ __global__ void __launch_bounds__(kBlock) k_nnz(NnzArgs A)
         const double W = A.degree == kBox3 ? (kap >= 0.0 ? 1.0 : 1.0 + fabs(kap))
                                            : 0.5 * (A.degree + 1) * (1.0 + fabs(kap));
         int jlo, jhi;
-        row_range(x0, kap, W, nmaj, nmin, &jlo, &jhi);
+        row_range(x0, kap, 1.0 / kap, W, nmaj, nmin, &jlo, &jhi);
         for (int j = jlo; j <= jhi; ++j) {
             const double X = x0 + kap * (double)j;
             // integers i in (X - W, X + W) within [0, nmin - 1]
