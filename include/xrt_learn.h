@@ -172,6 +172,28 @@ xrt_status xrt_solve(const xrt_plan* plan, float lambda, const float* b, float* 
                      xrt_unet* net, int32_t window, int32_t period, xrt_solve_info* info, double* history,
                      int32_t history_cap, void* stream);
 
+/* Options of the flexible CG of xrt_solve_ex. */
+typedef struct {
+    int32_t window;     /* FCG window m in [1, 16] */
+    int32_t period;     /* the network proposes on steps k = 0, period, 2 period, ... (>= 1) */
+    int32_t net_steps;  /* ... and only while k < net_steps; 0: on every such step.  After it, the
+                           steps take z_k = r_k and keep the M-orthogonalisation against the
+                           last m directions (CG-like steps that stay conjugate to the learned
+                           ones still in the window) */
+    int32_t restart;    /* 1 (needs net_steps > 0): the steps after the first net_steps are plain
+                           CG (Hestenes-Stiefel) restarted from the current iterate and residual
+                           instead of flexible steps; 0: as described above */
+} xrt_solve_opts;
+
+/* xrt_solve with options (opts is required when net != NULL and ignored
+ * otherwise); xrt_solve(..., window, period, ...) equals xrt_solve_ex with
+ * {window, period, 0, 0}.  Errors: those of xrt_solve; EINVAL for a null
+ * opts with a network, net_steps < 0, restart not 0 or 1, or restart with
+ * net_steps = 0. */
+xrt_status xrt_solve_ex(const xrt_plan* plan, float lambda, const float* b, float* x, float tol, int32_t maxit,
+                        xrt_unet* net, const xrt_solve_opts* opts, xrt_solve_info* info, double* history,
+                        int32_t history_cap, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

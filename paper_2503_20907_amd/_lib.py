@@ -38,7 +38,7 @@ EXPORTS = (
     "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_set_gain", "xrt_unet_get_gain",
     "xrt_unet_set_relu", "xrt_unet_apply", "xrt_unet_loss_grad", "xrt_unet_train_step",
     "xrt_unet_loss_grad_normal", "xrt_unet_train_step_normal", "xrt_conv3x3_forward",
-    "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve",
+    "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve", "xrt_solve_ex",
     # xrt_batch.h
     "xrt_batch_create", "xrt_batch_destroy", "xrt_batch_buffers", "xrt_batch_info", "xrt_batch_forward",
     "xrt_batch_adjoint", "xrt_batch_run", "xrt_batch_get_config", "xrt_batch_set_config",
@@ -62,6 +62,11 @@ class XrtSolveInfo(ctypes.Structure):
                 ("learned_accepted", ctypes.c_int32), ("learned_rejected", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double)]
+
+
+class XrtSolveOpts(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int32), ("period", ctypes.c_int32), ("net_steps", ctypes.c_int32),
+                ("restart", ctypes.c_int32)]
 
 
 class XrtProblem(ctypes.Structure):
@@ -130,6 +135,8 @@ def load() -> ctypes.CDLL:
     lib.xrt_conv3x3_grad_weight.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
     lib.xrt_solve.argtypes = [vp, f32, vp, vp, f32, i32, vp, i32, i32, ctypes.POINTER(XrtSolveInfo),
                               ctypes.POINTER(ctypes.c_double), i32, vp]
+    lib.xrt_solve_ex.argtypes = [vp, f32, vp, vp, f32, i32, vp, ctypes.POINTER(XrtSolveOpts),
+                                 ctypes.POINTER(XrtSolveInfo), ctypes.POINTER(ctypes.c_double), i32, vp]
     fpp = ctypes.POINTER(ctypes.c_void_p)
     lib.xrt_batch_create.argtypes = [ctypes.POINTER(XrtProblem), i32, vp, ctypes.POINTER(vp)]
     lib.xrt_batch_destroy.argtypes = [vp]
@@ -151,7 +158,8 @@ def load() -> ctypes.CDLL:
                  "xrt_normal_apply", "xrt_unet_create", "xrt_unet_num_params",
                  "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_apply",
                  "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
-                 "xrt_unet_train_step_normal", "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve"):
+                 "xrt_unet_train_step_normal", "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve",
+                 "xrt_solve_ex"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -300,6 +308,15 @@ def xrt_conv3x3_grad_input(gy, w, B, H, W, cin, cout, gx, stream) -> int:
 
 def xrt_conv3x3_grad_weight(x, gy, B, H, W, cin, cout, gw, stream) -> int:
     return load().xrt_conv3x3_grad_weight(x, gy, int(B), int(H), int(W), int(cin), int(cout), gw, stream)
+
+
+def xrt_solve_ex(plan, lam, b, x, tol, maxit, net, window, period, net_steps, restart, history_cap, stream):
+    info = XrtSolveInfo()
+    opts = XrtSolveOpts(int(window), int(period), int(net_steps), int(restart))
+    hist = (ctypes.c_double * max(1, int(history_cap)))()
+    st = load().xrt_solve_ex(plan, float(lam), b, x, float(tol), int(maxit), net, ctypes.byref(opts),
+                             ctypes.byref(info), hist if history_cap > 0 else None, int(history_cap), stream)
+    return st, info, [hist[i] for i in range(min(int(history_cap), info.iterations))]
 
 
 def xrt_solve(plan, lam, b, x, tol, maxit, net, window, period, history_cap, stream):

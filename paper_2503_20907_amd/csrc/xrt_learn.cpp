@@ -698,8 +698,27 @@ xrt_status xrt_solve(const xrt_plan* plan, float lambda, const float* b, float* 
                      xrt_unet* net, int32_t window, int32_t period, xrt_solve_info* info, double* history,
                      int32_t history_cap, void* stream)
 {
+    xrt_solve_opts o;
+    o.window = window;
+    o.period = period;
+    o.net_steps = 0;
+    o.restart = 0;
+    return xrt_solve_ex(plan, lambda, b, x, tol, maxit, net, net ? &o : nullptr, info, history, history_cap,
+                        stream);
+}
+
+xrt_status xrt_solve_ex(const xrt_plan* plan, float lambda, const float* b, float* x, float tol, int32_t maxit,
+                        xrt_unet* net, const xrt_solve_opts* opts, xrt_solve_info* info, double* history,
+                        int32_t history_cap, void* stream)
+{
     if (!b || !x || !info || !(tol > 0.f) || maxit < 0) return XRT_EINVAL;
-    if (net && (window < 1 || window > xrl::kMaxVecs || period < 1)) return XRT_EINVAL;
+    if (net && !opts) return XRT_EINVAL;
+    const int32_t window = net ? opts->window : 1, period = net ? opts->period : 1;
+    const int32_t net_steps = net ? opts->net_steps : 0;
+    const bool restart = net && opts->restart != 0;
+    if (net && (window < 1 || window > xrl::kMaxVecs || period < 1 || net_steps < 0)) return XRT_EINVAL;
+    if (net && (opts->restart != 0 && opts->restart != 1)) return XRT_EINVAL;
+    if (restart && net_steps == 0) return XRT_EINVAL;
     int64_t m = 0, crossing = 0;
     xrt_status st = xrt_plan_info(plan, &m, &crossing);
     if (st != XRT_OK) return st;
@@ -784,7 +803,11 @@ xrt_status xrt_solve(const xrt_plan* plan, float lambda, const float* b, float* 
                 cnt = head = 0;
             }
             if (info->iterations >= maxit) break;
-            if (!net) {
+            // with `restart`, the steps after the first net_steps are plain CG, started
+            // afresh from the current iterate and residual
+            const bool cg_step = !net || (restart && info->iterations >= net_steps);
+            if (restart && info->iterations == net_steps) have_prev = false;
+            if (cg_step) {
                 // conjugate gradients (Hestenes-Stiefel)
                 if (!have_prev) {
                     XS(hipMemcpyAsync(p, r, n * sizeof(float), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
@@ -800,8 +823,9 @@ xrt_status xrt_solve(const xrt_plan* plan, float lambda, const float* b, float* 
                 rel = sqrt(host[S_RR]) / bn;
             } else {
                 // flexible CG: the new direction is M-orthogonalised against the last `win` ones;
-                // the network proposes every `period`-th step, the others take z = r
-                bool learned = info->iterations % period == 0;
+                // the network proposes every `period`-th step (within the first net_steps
+                // steps when net_steps > 0), the others take z = r
+                bool learned = info->iterations % period == 0 && (net_steps == 0 || info->iterations < net_steps);
                 for (;;) {
                     const float* zz = r;
                     if (learned) {

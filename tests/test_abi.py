@@ -139,6 +139,16 @@ def test_learn_entry_points_reject_bad_arguments():
                          ctypes.byref(info), None, 0, None) == L.XRT_EPLAN
     assert lib.xrt_solve(1, ctypes.c_float(1.0), 1, 1, ctypes.c_float(0.0), 10, None, 1, 1,
                          ctypes.byref(info), None, 0, None) == L.XRT_EINVAL
+    # xrt_solve_ex: the options are checked before the plan or the network is
+    # read (a dummy non-null network pointer is never dereferenced here)
+    assert lib.xrt_solve_ex(None, ctypes.c_float(1.0), 1, 1, ctypes.c_float(1e-3), 10, None, None,
+                            ctypes.byref(info), None, 0, None) == L.XRT_EPLAN
+    assert lib.xrt_solve_ex(1, ctypes.c_float(1.0), 1, 1, ctypes.c_float(1e-3), 10, 1, None,
+                            ctypes.byref(info), None, 0, None) == L.XRT_EINVAL
+    for bad in [(0, 1, 0, 0), (17, 1, 0, 0), (1, 0, 0, 0), (1, 1, -1, 0), (1, 1, 0, 1), (1, 1, 2, 2)]:
+        o = L.XrtSolveOpts(*bad)
+        assert lib.xrt_solve_ex(1, ctypes.c_float(1.0), 1, 1, ctypes.c_float(1e-3), 10, 1, ctypes.byref(o),
+                                ctypes.byref(info), None, 0, None) == L.XRT_EINVAL, bad
     # convolutions need channel counts that are multiples of 32
     assert lib.xrt_conv3x3_forward(1, 1, 1, 8, 8, 16, 32, 0, 1, None) == L.XRT_EINVAL
     assert lib.xrt_conv3x3_grad_weight(1, 1, 1, 8, 8, 32, 48, 1, None) == L.XRT_EINVAL

@@ -190,19 +190,24 @@ def test_normal_apply_matches_oracle(dev, learn, small_recon):
     assert rel(out, R.normal_apply(s["n"], c, s["lc"], s["lam"])) < 1e-5
 
 
-@pytest.mark.parametrize("use_net", [False, True])
+@pytest.mark.parametrize("use_net", [False, True, "restart"])
 def test_solver_reaches_tolerance_by_oracle_residual(dev, learn, small_recon, use_net):
     s = small_recon
     net = learn.UNet(s["N"], s["N"], levels=3, base=32, max_batch=1, seed=5) if use_net else None
     b = torch.as_tensor(s["b"].astype(np.float32), device=dev)
-    x, info = learn.solve(s["plan"], b, s["lam"], tol=1e-3, maxit=3000, net=net, history=4000)
+    kw = {"net_steps": 2, "restart": True} if use_net == "restart" else {}
+    x, info = learn.solve(s["plan"], b, s["lam"], tol=1e-3, maxit=3000, net=net, history=4000, **kw)
     assert info["converged"]
     xo = x.cpu().numpy().astype(np.float64)
     bo = s["b"].astype(np.float32).astype(np.float64)
     res = np.linalg.norm(bo - R.normal_apply(s["n"], xo, s["lc"], s["lam"])) / np.linalg.norm(bo)
     assert res <= 1.02e-3, res
     assert abs(res - info["rel_residual"]) < 5e-5
-    if use_net:
+    if use_net == "restart":
+        # the network proposes on the first two steps only, then CG takes over
+        assert info["learned_accepted"] + info["learned_rejected"] == min(2, info["iterations"])
+        net.close()
+    elif use_net:
         assert info["learned_accepted"] + info["learned_rejected"] >= info["iterations"]
         net.close()
 
