@@ -81,11 +81,16 @@ def cpu_baseline(spec, coeffs, degree, n_lines_total, seconds_target=15.0):
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1
 
-    k = 1024
-    tf, ta = run(k)
-    per = (tf + ta) / k
-    k2 = int(max(1024, min(200000, seconds_target / max(per, 1e-9))))
-    tf, ta = run(k2)
+    # time = fixed + k * per_line (the ray-major adjoint has a fixed cost: one
+    # FP64 image per thread); two sizes fix both, the third run is the sample
+    k1, k2 = 1024, 8192
+    t1 = sum(run(k1))
+    t2 = sum(run(k2))
+    per = max((t2 - t1) / (k2 - k1), 1e-9)
+    fixed = max(t1 - k1 * per, 0.0)
+    k3 = int(max(k2, min(400000, (seconds_target - fixed) / per)))
+    tf, ta = run(k3)
+    k2 = k3
     rate = k2 / (tf + ta)
     return {"value": rate / 1e9, "unit": "Gray/s", "cores": threads, "kind": "oracle",
             "sample": f"{k2} random lines of the workload, forward + ray-major adjoint "
