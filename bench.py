@@ -33,6 +33,18 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 G
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_source_hash(path: str) -> str:
+    """SHA-256 (first 16 hex digits) of a source file with its comments and
+    whitespace removed: it changes when the code does, not when a comment does."""
+    import hashlib
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"\s+", "", text)
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
     (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or None if
@@ -43,7 +55,7 @@ def measured_traffic(kernel: str):
     summ = os.path.join(ROOT, "profiles", "hbm_traffic_2048_cubic_fan_random.md")
     if not (os.path.exists(src) and os.path.exists(summ)):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_hash(src)
     total = 0
     found = False
     for line in open(summ):

@@ -383,35 +383,6 @@ __device__ inline void row_core(double q, const LineConst& k, const float4* __re
     for (int sl = 1; sl < S; ++sl) R.g[sl] = etab64<N>(tab, fmaf(-(float)sl, k.inv64, a0));
 }
 
-// Weights of the taps J - d: beta^n(t + d - (n+1)/2), plus the
-// r^2 (mu_2/2) beta^n'' term (rho) for n >= 2.
-template <int N>
-__device__ inline void tap_weights(float t, float rho, float* w)
-{
-    if constexpr (N == 0) {
-        w[0] = 1.f;
-    } else if constexpr (N == 1) {
-        w[0] = t;
-        w[1] = 1.f - t;
-    } else if constexpr (N == 2) {
-        const float u = t - 0.5f, s = 1.f - t;
-        w[0] = fmaf(0.5f * t, t, rho);
-        w[1] = fmaf(-u, u, fmaf(-2.f, rho, 0.75f));
-        w[2] = fmaf(0.5f * s, s, rho);
-    } else {
-        // with h2 = (t^2 + 2 rho)/2 and h3 = t (t^2 + 6 rho)/6:
-        //   w0 = h3, w3 = 1/6 - t/2 + h2 - h3, w1 = 1/6 + t/2 + h2 - 3 h3,
-        //   w2 = 2/3 - 2 h2 + 3 h3
-        const float h2 = fmaf(0.5f * t, t, rho);
-        const float h3 = (t * (1.f / 6.f)) * fmaf(t, t, 6.f * rho);
-        const float u = (1.f / 6.f) + h2 - h3;
-        w[0] = h3;
-        w[3] = fmaf(-0.5f, t, u);
-        w[1] = fmaf(0.5f, t, fmaf(-2.f, h3, u));
-        w[2] = fmaf(3.f, h3, fmaf(-2.f, h2, 2.f / 3.f));
-    }
-}
-
 // sum_d w_d(t) c_{J-d} written in powers of t, times kTapScale<N> (c[0] is
 // c_{J-N}, c[N] is c_J).  For n = 3:
 //   6 S = (c0 + 4c1 + c2) + 3t (c2 - c0) + 3(t^2 + 2 rho)(c0 - 2c1 + c2)
@@ -818,7 +789,13 @@ __device__ inline int fixed_round(float a, float b)
     return __float_as_int(fmaf(a, b, kRoundMagic)) - kRoundMagicBits;
 }
 
-// The tap weights of tap_weights<N> times a line constant sigma, rounded to
+// The weights of the taps J - d: beta^n(t + d - (n+1)/2), plus the
+// r^2 (mu_2/2) beta^n'' term (rho) for n >= 2.  Degree 1: t, 1 - t.
+// Degree 2: t^2/2 + rho, 3/4 - 2 rho - (t - 1/2)^2, (1 - t)^2/2 + rho.
+// Degree 3, with h2 = (t^2 + 2 rho)/2 and h3 = t (t^2 + 6 rho)/6:
+//   w0 = h3, w3 = 1/6 - t/2 + h2 - h3, w1 = 1/6 + t/2 + h2 - 3 h3,
+//   w2 = 2/3 - 2 h2 + 3 h3.
+// The adjoint needs them times a line constant sigma, rounded to
 // integers as fixed_round does: the round-to-nearest-even constant
 // kRoundMagic is carried in per-line coefficients (and in the last
 // multiply-add of each weight), and sigma is folded into the coefficients,
@@ -874,8 +851,8 @@ __device__ inline void tap_fixed(float t, const TapScaled<N>& k, int* wi)
         wi[1] = magic_int(fmaf(-k.a * u, u, k.c));
         wi[2] = magic_int(fmaf(k.d * s, s, k.b));
     } else {
-        // as tap_weights<3>, every term times sigma:
-        //   h2 = sigma (t^2 + 2 rho)/2, h3 = sigma t (t^2 + 6 rho)/6, u = sigma/6 + h2 - h3
+        // every term times sigma: h2 = sigma (t^2 + 2 rho)/2,
+        // h3 = sigma t (t^2 + 6 rho)/6, u = sigma/6 + h2 - h3
         const float ct = k.c * t, p = fmaf(t, t, k.d);
         const float h3 = ct * p;
         const float h2 = fmaf(k.a * t, t, k.b);
