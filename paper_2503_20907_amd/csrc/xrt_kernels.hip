@@ -869,9 +869,10 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
                                 const LineConst& lc, int W, const float4* __restrict__ s_tab,
                                 int* s_a, int* s_k)
 {
-    // start each lane at a different row so that the lanes of a wave rarely
-    // update the same LDS word in one instruction
-    int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
+    // start each lane at a different row (spread over [0, cnt) by a
+    // multiply and shift) so that the lanes of a wave rarely update the same
+    // LDS word in one instruction
+    int jj = (int)((((threadIdx.x * 13u) & 255u) * (unsigned)cnt) >> 8);
     const float svkr = svk * lc.rn;
     const TapScaled<N> tk = tap_scaled<N>(svs, lc.rho);
     // knot slots start at K0 = J + o, o = 1 - S/2 for even S (a constant), so
@@ -901,7 +902,7 @@ template <bool NEG>
 __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, float svs, const BoxRow& bk,
                                     int W, int* s_a)
 {
-    int jj = (int)((threadIdx.x * 13u) % (unsigned)cnt);
+    int jj = (int)((((threadIdx.x * 13u) & 255u) * (unsigned)cnt) >> 8);
     for (int c = 0; c < cnt; ++c) {
         // q > 0 (halo-relative column), so truncation is the floor
         const double q = fma(kap, (double)jj, q0);
@@ -1027,6 +1028,7 @@ struct AdjShared {
     uint32_t start[kSlopeBins];
     uint32_t pre[kSlopeBins + 1];
     uint32_t scan[kBlock];
+    uint32_t run[16];   // slope bins of the first and last item of each run of 64 items of a chunk
     float red[4];
 };
 
@@ -1123,16 +1125,35 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
         const uint32_t total = s_pre[kSlopeBins];
 
         for (uint32_t base = (uint32_t)kpart * 2u * kBlock; base < total; base += (uint32_t)A.split * 2u * kBlock) {
+            // item -> slope bin b with s_pre[b] <= item < s_pre[b+1].  Each
+            // wave takes runs of 64 consecutive items; 16 threads first find
+            // the bins of every run's first and last item, so that a lane
+            // then searches only the few bins its run spans.
+            if (tid < 16) {
+                const uint32_t first = base + (uint32_t)((tid >> 3) * kBlock + ((tid >> 1) & 3) * 64);
+                uint32_t it = first;
+                if (tid & 1) it = min(first + 63u, total - 1u);
+                int lo = 0, hi = kSlopeBins;
+                if (first < total) {
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= it) lo = mid;
+                        else hi = mid;
+                    }
+                }
+                sh.run[tid] = (uint32_t)lo;
+            }
+            __syncthreads();
             uint32_t kk[2] = {0, 0};
             float svv[2] = {0.f, 0.f};
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const uint32_t item = base + (uint32_t)(u * kBlock + tid);
                 if (item < total) {
-                    // bin b with s_pre[b] <= item < s_pre[b+1]
-                    int lo = 0, hi = kSlopeBins;
+                    const int r = (u << 3) | ((tid >> 6) << 1);
+                    int lo = (int)sh.run[r], hi = (int)sh.run[r + 1] + 1;
                     while (hi - lo > 1) {
-                        int mid = (lo + hi) >> 1;
+                        const int mid = (lo + hi) >> 1;
                         if (s_pre[mid] <= item) lo = mid;
                         else hi = mid;
                     }
@@ -1146,6 +1167,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
             (void)frexpf(mx, &em);
             // |s| 2^e < 2^21 (every row weight is at most 1)
             const int e = 21 - em;
+            const double kscale = ldexp(1.0, -e - knot_shift<N>());
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if constexpr (N == kBox3)
@@ -1167,10 +1189,13 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                     o[q] += ldexpf((float)ar[0], -e);
                 } else {
                     const int* kr = s_k + lmaj * W + kHalo + lmin;
-                    long long v = 0;
+                    // the (n+1)-th difference of integers below 2^30 (at most
+                    // 2^35 in magnitude) is exact in FP64; scaled by a power of
+                    // two, then rounded once to FP32
+                    double v = 0.0;
 #pragma unroll
-                    for (int l = 0; l <= N + 1; ++l) v += (long long)delta_w<N>(l) * kr[l];
-                    o[q] += ldexpf((float)ar[0], -e) + ldexpf((float)v, -e - knot_shift<N>());
+                    for (int l = 0; l <= N + 1; ++l) v = fma((double)delta_w<N>(l), (double)kr[l], v);
+                    o[q] += ldexpf((float)ar[0], -e) + (float)(v * kscale);
                 }
             }
             __syncthreads();
