@@ -11,10 +11,13 @@ Tikhonov normal equations (lambda 1e-2) on a 512 x 512 cubic grid with
 180 x 768 parallel-beam Poisson-noisy data, plain CG against flexible CG with
 the trained U-Net preconditioner (training time reported separately).
 
-It also carries "batch": 64 uneven problems in one persistent launch per
-direction (with graph replay and the autotuner) against per-problem plans.
+It also carries "batch": 64 uneven problems in persistent launches (one for
+the forward, two for the adjoint; with graph replay and the autotuner) against
+per-problem plans, and "box3": the 3-directional box spline on the same lines
+and grid.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline] [--no-recon] [--no-batch]
+                    [--no-box]
 """
 from __future__ import annotations
 
@@ -260,7 +263,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
-              "(every box has one GPU; the multi-GPU layout is a design note only)",
+              "(the multi-GPU layout is a design note only)",
               file=sys.stderr)
         sys.exit(2)
 
