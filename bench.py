@@ -186,8 +186,8 @@ def recon_leg(log):
 
 def batch_leg(log):
     """64 uneven problems (sizes 128..1024, degrees 1 and 3, 60..720 views,
-    parallel or fan): per-problem plans one after another vs one persistent
-    launch per direction, eager and replayed as a HIP graph, before and after
+    parallel or fan): per-problem plans one after another vs the batch's
+    persistent launches, eager and replayed as a HIP graph, before and after
     the autotuner.  Rates in lines per second over the whole batch."""
     import torch
 

@@ -1,7 +1,7 @@
 /*
- * xrt_batch.h -- many x-ray transform problems of uneven size in one
- * persistent launch per direction, optionally replayed as a HIP graph, with
- * a run-time autotuner.  C ABI of libxrt.so.
+ * xrt_batch.h -- many x-ray transform problems of uneven size in
+ * persistent launches (one for the forward, two for the adjoint), optionally
+ * replayed as a HIP graph, with a run-time autotuner.  C ABI of libxrt.so.
  *
  * Each problem is what xrt_plan_create takes (a grid, a degree 0..3 or
  * XRT_BOX3, a line list, eq. (4) and its adjoint as in xrt.h); problems of
