@@ -9,7 +9,7 @@
 // where psi_r = beta^n * beta^n_r is the footprint of Proposition 1 / eq. (6)
 // written in units of the row (phi_theta(u) = psi_r(u/|sin t|)/|sin t|).
 //
-// psi_r is split exactly (derived from eq. (6), see the design notes) as
+// psi_r is split exactly (an identity derived from eq. (6)) as
 //     psi_r(v) = S_r(v) + sum_k delta_k r^n E((v - kappa_k)/r),
 //     S_r = beta^n + [n >= 2] r^2 (mu_2/2) beta^n'',
 //     delta_k = (-1)^k C(n+1, k),  kappa_k = k - (n+1)/2 (knots of beta^n),
@@ -28,7 +28,13 @@
 //
 // The adjoint applies the transpose of exactly the same row arithmetic:
 // every line adds W_d s to the cells J-d and r^n E(.) s to the knots K of an
-// LDS tile, and the tile's output is A + Delta^T K, written once.
+// LDS tile, and the tile's output is A + Delta^T K.  One launch takes the
+// vertical lines and writes the image, a second one the horizontal lines and
+// adds into it; each tile's pixels are written by one workgroup per launch.
+//
+// The 3-directional box spline (basis code kBox3) uses the same schedules
+// with its own row arithmetic (box_row, box_F): a telescoped row sum over two
+// or four columns instead of taps and knots.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -1263,12 +1269,13 @@ struct BatchArgs {
     int lines_per_item;  // forward: lines per item, a multiple of kBlock
 };
 
-// Many problems (each with its own plan) in one persistent launch per
-// direction.  Work items (problem, block of lines) for the forward and
-// (problem, tile) for the adjoint are listed largest problem first; every
-// workgroup takes the next item from one atomic counter until the list is
-// exhausted (the only atomic: the adjoint of an item is the gather of one
-// tile, written once).
+// Many problems (each with its own plan) in persistent launches: one for the
+// forward, two for the adjoint (one per orientation).  Work items (problem,
+// block of lines) for the forward and (problem, tile) for the adjoint are
+// listed largest problem first; every workgroup takes the next item from its
+// launch's atomic counter until the list is exhausted (the only atomics on
+// global memory: the adjoint of an item is the gather of one tile, whose
+// pixels only that workgroup writes in that launch).
 // Line k over the rows of strip `st` (unscaled sum into spart[st][k]).
 template <int N, bool VERT>
 __device__ inline void fwd_line_strip(const BatchProb& P, int64_t k, int st, const float4* __restrict__ s_tab)
