@@ -282,3 +282,30 @@ def test_large_sampled(orc, torch, ops):
     lhs = float(np.dot(got.astype(np.float64), sv.astype(np.float64)))
     rhs = float(np.dot(coeffs.astype(np.float64).ravel(), got_a.astype(np.float64)))
     assert abs(lhs - rhs) <= TOL * abs(lhs)
+
+
+def test_large_sampled_box_spline(orc, torch, ops):
+    """The same 2048^2 lines with the 3-directional box spline (as the
+    benchmark times it): forward at 200 sampled lines, adjoint at 40 sampled
+    pixels, and the adjoint identity over the whole operator."""
+    say("case: 2048 box spline fan+random")
+    box = orc.BOX3
+    spec, nfan = W.large_lines()
+    coeffs = W.large_phantom()
+    lines = ops.Lines.from_spec(spec)
+    plan = ops.Plan(2048, 2048, box, lines)
+    got = plan.forward(to_dev(torch, coeffs)).cpu().numpy()
+    Lo = orc_lines(orc, spec)
+    rng = np.random.default_rng(801)
+    pick = rng.choice(lines.n, size=200, replace=False)
+    ref = orc.forward(box, coeffs.astype(np.float64), tuple(v[pick] for v in Lo))
+    assert rel_l2(got[pick], ref) <= TOL
+    sv = rng.normal(size=lines.n).astype(np.float32)
+    got_a = plan.adjoint(to_dev(torch, sv)).cpu().numpy().ravel()
+    pix = rng.choice(2048 * 2048, size=40, replace=False)
+    ref_a = orc.adjoint_pixels(box, sv.astype(np.float64), Lo, 2048, 2048, pix)
+    assert rel_l2(got_a[pix], ref_a) <= TOL
+    lhs = float(np.dot(got.astype(np.float64), sv.astype(np.float64)))
+    rhs = float(np.dot(coeffs.astype(np.float64).ravel(), got_a.astype(np.float64)))
+    assert abs(lhs - rhs) <= TOL * abs(lhs)
+    plan.close()
