@@ -10,6 +10,9 @@ import torch
 
 from . import _lib as L
 
+# basis code of the 3-directional box spline (degrees 0..3 are the tensor B-splines)
+BOX3 = L.XRT_BOX3
+
 
 def _stream() -> int:
     return int(torch.cuda.current_stream().cuda_stream)
