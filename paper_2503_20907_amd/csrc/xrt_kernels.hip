@@ -22,9 +22,10 @@
 // (plus the r^2 beta'' term), and D_K = sum_l delta_l c_{K-l} the (n+1)-th
 // backward difference of the row at knot K.  At most n+1 knots K lie within
 // (n+1) r / 2 of X, so a row costs n+1 taps plus n+1 knot slots whatever r
-// is.  E is held in LDS as a cubic-per-interval table (64 intervals per unit)
-// built in FP64 on the host.  Line geometry (crossings, floors) is FP64; the
-// row arithmetic is FP32 in local coordinates t in [0, 1).
+// is.  E is a cubic-per-interval table (64 intervals per unit) built in FP64
+// on the host and copied to LDS; the adjoint reads part of its entries from
+// the global copy instead (adj_mem_slots).  Line geometry (crossings, floors)
+// is FP64; the row arithmetic is FP32 in local coordinates t in [0, 1).
 //
 // The adjoint applies the transpose of exactly the same row arithmetic:
 // every line adds W_d s to the cells J-d and r^n E(.) s to the knots K of an
@@ -346,14 +347,28 @@ __device__ inline int wave_slots(int mine)
 
 // Knot-transition table at z64 = 64 z: g(|z|) with the parity of E
 // (E is even for odd n; for even n it changes sign at 0).
-template <int N>
-__device__ inline float etab64(const float4* __restrict__ tab, float z64)
+// Table entries are read as a uniform base plus a 32-bit byte offset.  The
+// global copy is typed in the global address space: through a generic pointer
+// the compiler would issue flat loads, whose waits also drain the LDS queue.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const f4v GTab;
+typedef __attribute__((address_space(1))) const char GByte;
+
+__device__ inline f4v tab_at(const float4* tab, uint32_t byte)
+{
+    const float4 v = *(const float4*)((const char*)tab + byte);
+    return f4v{v.x, v.y, v.z, v.w};
+}
+__device__ inline f4v tab_at(const GTab* tab, uint32_t byte) { return *(const GTab*)((const GByte*)tab + byte); }
+
+template <int N, typename T>
+__device__ inline float etab64(const T* __restrict__ tab, float z64)
 {
     constexpr int last = kTabPerUnit * (N + 1) / 2;  // index of the zero interval
     const float a = fminf(fabsf(z64), (float)last);
     const int i = (int)a;
     const float tau = __builtin_amdgcn_fractf(a);
-    const float4 cf = tab[i];
+    const f4v cf = tab_at(tab, (uint32_t)i << 4);
     float g = fmaf(tau, fmaf(tau, fmaf(tau, cf.w, cf.z), cf.y), cf.x);
     if constexpr (N % 2 == 0) g = z64 >= 0.f ? -g : g;
     return g;
@@ -368,9 +383,17 @@ struct Row {
     float g[S];
 };
 
-template <int N, int S>
-__device__ inline void row_core(double q, const LineConst& k, const float4* __restrict__ tab,
-                                Row<S>& R)
+// The two copies of the E table a row reads: knot slots below G take the
+// global copy (through the vector L1 cache), the others the LDS copy.  The
+// forward reads all of them from LDS (G = 0): its vector memory path is busy
+// with the coefficient loads.
+struct TabRef {
+    const float4* lds;
+    const GTab* mem;
+};
+
+template <int N, int S, int G = 0>
+__device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>& R)
 {
     // q > 0 here (a padded or halo-relative column coordinate), so truncation
     // is the floor
@@ -384,9 +407,12 @@ __device__ inline void row_core(double q, const LineConst& k, const float4* __re
     R.K0 = R.J + o;
     // z_s = (q - K0 - s) / r, in table units
     const float a0 = (t - (float)o) * k.inv64;
-    R.g[0] = etab64<N>(tab, a0);
+    R.g[0] = G > 0 ? etab64<N>(tab.mem, a0) : etab64<N>(tab.lds, a0);
 #pragma unroll
-    for (int sl = 1; sl < S; ++sl) R.g[sl] = etab64<N>(tab, fmaf(-(float)sl, k.inv64, a0));
+    for (int sl = 1; sl < S; ++sl) {
+        const float z = fmaf(-(float)sl, k.inv64, a0);
+        R.g[sl] = sl < G ? etab64<N>(tab.mem, z) : etab64<N>(tab.lds, z);
+    }
 }
 
 // sum_d w_d(t) c_{J-d} written in powers of t, times kTapScale<N> (c[0] is
@@ -564,7 +590,7 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     float part = 0.f;
     for (int j = ja; j <= jb; ++j) {
         Row<S> R;
-        row_core<N, S>(q, lc, tab, R);
+        row_core<N, S>(q, lc, TabRef{tab, nullptr}, R);
         float cv[N + 1], dv[S];
         load_run<N + 1>((const float*)(Cb + (off + (uint32_t)(R.J - N) * 4u)), cv);
         load_run<S>((const float*)(Db + (off + (uint32_t)R.K0 * 4u)), dv);
@@ -870,9 +896,24 @@ __device__ inline void tap_fixed(float t, const TapScaled<N>& k, int* wi)
     }
 }
 
-template <int N, int S>
+// Knot slots per row whose E value the adjoint reads from the global table
+// copy (through the vector L1) rather than from LDS.  A row makes N + 1 tap and
+// S knot atomics on LDS, and the S table reads queue behind them there; moving
+// (N + 1)/2 of the reads to the idle L1 shortens the queue (2048^2, 8.85M
+// lines: cubic 32.4 -> 28.3 ms, quadratic 25.4 -> 23.7, linear 18.8 -> 18.1).
+// More than that loads the L1 path instead (three of four cubic reads: no
+// gain; the constant spline, with one atomic pair per row, loses).  The
+// batch's persistent workgroups keep every read on LDS (L1 = false): there the
+// split made the 64-problem adjoint slower, 14.0 -> 15.0 ms.
+template <int N, int S, bool L1>
+__device__ constexpr int adj_mem_slots()
+{
+    return !L1 ? 0 : S < (N + 1) / 2 ? S : (N + 1) / 2;
+}
+
+template <int N, int S, bool L1>
 __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float svs, float svk,
-                                const LineConst& lc, int W, const float4* __restrict__ s_tab,
+                                const LineConst& lc, int W, TabRef s_tab,
                                 int* s_a, int* s_k)
 {
     // start each lane at a different row (spread over [0, cnt) by a
@@ -887,7 +928,7 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     for (int c = 0; c < cnt; ++c) {
         const double q = fma(kap, (double)jj, q0);
         Row<S> R;
-        row_core<N, S>(q, lc, s_tab, R);
+        row_core<N, S, adj_mem_slots<N, S, L1>()>(q, lc, s_tab, R);
         int wi[N + 1];
         tap_fixed<N>(R.t, tk, wi);
         const uint32_t base = __umul24((uint32_t)(row0 + jj), (uint32_t)W) + (uint32_t)(R.J - N);
@@ -963,10 +1004,10 @@ __device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, f
     else adj_walk_box<false>(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
 }
 
-template <int N>
+template <int N, bool L1>
 __device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float sv, int e,
                                 bool vert, int maj0, int min0, int TM, int TN, int nmaj, int W,
-                                double jc, double marg, const float4* __restrict__ s_tab, int* s_a,
+                                double jc, double marg, TabRef s_tab, int* s_a,
                                 int* s_k)
 {
     const double H = 0.5 * (N + 1);
@@ -1004,10 +1045,10 @@ __device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float
     // local q: column index within the LDS row (halo included)
     const double q0 = x0 + kap * (double)ra + H - (double)min0 + (double)kHalo;
     const int cnt = rb - ra + 1, row0 = ra - maj0;
-    if (S == 1) adj_walk<N, 1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
-    else if (S == 2) adj_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
-    else if (S == 3) adj_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
-    else adj_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    if (S == 1) adj_walk<N, 1, L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    else if (S == 2) adj_walk<N, (N >= 1 ? 2 : 1), L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    else if (S == 3) adj_walk<N, (N >= 2 ? 3 : 1), L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    else adj_walk<N, (N >= 3 ? 4 : 1), L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
 }
 
 __device__ inline float block_max(float v, float* red)
@@ -1053,13 +1094,13 @@ __device__ constexpr int adj_tj() { return MODE == kAdjHoriz ? kTileI : kTileJ; 
 // One pixel tile of the adjoint; `kpart` selects this workgroup's share of
 // the candidate chunks when A.split > 1.  The table must already be in
 // sh.tab.
-template <int N, int MODE>
+template <int N, int MODE, bool L1 = true>
 __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, AdjShared& sh)
 {
     constexpr int TI = adj_ti<MODE>(), TJ = adj_tj<MODE>();
     int* s_a = sh.a;
     int* s_k = sh.k;
-    const float4* s_tab = sh.tab;
+    const TabRef s_tab{sh.tab, (const GTab*)A.tab};
     uint32_t* s_start = sh.start;
     uint32_t* s_pre = sh.pre;
     uint32_t* s_scan = sh.scan;
@@ -1180,7 +1221,7 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                     adj_line_box(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg,
                                  s_a);
                 else
-                    adj_line<N>(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
+                    adj_line<N, L1>(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
                                 jc, marg, s_tab, s_a, s_k);
             }
             __syncthreads();
@@ -1381,11 +1422,11 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs
             __syncthreads();
         }
         switch (deg) {
-        case 0: adj_tile<0, MODE>(A, w.y, 0, sh); break;
-        case 1: adj_tile<1, MODE>(A, w.y, 0, sh); break;
-        case 2: adj_tile<2, MODE>(A, w.y, 0, sh); break;
-        case 3: adj_tile<3, MODE>(A, w.y, 0, sh); break;
-        default: adj_tile<kBox3, MODE>(A, w.y, 0, sh); break;
+        case 0: adj_tile<0, MODE, false>(A, w.y, 0, sh); break;
+        case 1: adj_tile<1, MODE, false>(A, w.y, 0, sh); break;
+        case 2: adj_tile<2, MODE, false>(A, w.y, 0, sh); break;
+        case 3: adj_tile<3, MODE, false>(A, w.y, 0, sh); break;
+        default: adj_tile<kBox3, MODE, false>(A, w.y, 0, sh); break;
         }
     }
 }
