@@ -402,11 +402,18 @@ __device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>
     R.t = t;
     // the S knots nearest to q: centred on round(q) for odd S, on q for even S
     int o;
-    if constexpr (S % 2 == 1) o = (t >= 0.5f ? 1 : 0) - (S - 1) / 2;
-    else o = 1 - S / 2;
+    float oz;  // o / r in table units (loop-invariant choices)
+    if constexpr (S % 2 == 1) {
+        const bool up = t >= 0.5f;
+        o = (up ? 1 : 0) - (S - 1) / 2;
+        oz = up ? (float)(1 - (S - 1) / 2) * k.inv64 : (float)(-((S - 1) / 2)) * k.inv64;
+    } else {
+        o = 1 - S / 2;
+        oz = (float)o * k.inv64;
+    }
     R.K0 = R.J + o;
     // z_s = (q - K0 - s) / r, in table units
-    const float a0 = (t - (float)o) * k.inv64;
+    const float a0 = fmaf(t, k.inv64, -oz);
     R.g[0] = G > 0 ? etab64<N>(tab.mem, a0) : etab64<N>(tab.lds, a0);
 #pragma unroll
     for (int sl = 1; sl < S; ++sl) {
@@ -588,12 +595,15 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     uint32_t off = (uint32_t)ja * (uint32_t)pitch * 4u;
     const uint32_t step = (uint32_t)pitch * 4u;
     float part = 0.f;
+    // walk q - N (exact): its floor is the first tap J - N, so that the taps
+    // and the knot slots (at J - N + N + o) share one offset register
+    q -= (double)N;
     for (int j = ja; j <= jb; ++j) {
         Row<S> R;
         row_core<N, S>(q, lc, TabRef{tab, nullptr}, R);
         float cv[N + 1], dv[S];
-        load_run<N + 1>((const float*)(Cb + (off + (uint32_t)(R.J - N) * 4u)), cv);
-        load_run<S>((const float*)(Db + (off + (uint32_t)R.K0 * 4u)), dv);
+        load_run<N + 1>((const float*)(Cb + (off + (uint32_t)R.J * 4u)), cv);
+        load_run<S>((const float*)(Db + (off + (uint32_t)(R.K0 + N) * 4u)), dv);
         float es = R.g[0] * dv[0];
 #pragma unroll
         for (int sl = 1; sl < S; ++sl) es = fmaf(R.g[sl], dv[sl], es);
@@ -925,13 +935,18 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     // knot slots start at K0 = J + o, o = 1 - S/2 for even S (a constant), so
     // that taps and slots share one base address at J - N
     constexpr int kEven = 1 - S / 2 + N;
-    for (int c = 0; c < cnt; ++c) {
-        const double q = fma(kap, (double)jj, q0);
+    // walk q - N (exact): its floor is the first tap J - N (at least 0: the
+    // halo covers the footprint), which is the base address of the row
+    const double q0n = q0 - (double)N;
+    // every row once, from jj round to jj (cnt >= 1)
+    const int jstart = jj;
+    do {
+        const double q = fma(kap, (double)jj, q0n);
         Row<S> R;
         row_core<N, S, adj_mem_slots<N, S, L1>()>(q, lc, s_tab, R);
         int wi[N + 1];
         tap_fixed<N>(R.t, tk, wi);
-        const uint32_t base = __umul24((uint32_t)(row0 + jj), (uint32_t)W) + (uint32_t)(R.J - N);
+        const uint32_t base = __umul24((uint32_t)(row0 + jj), (uint32_t)W) + (uint32_t)R.J;
         int* ar = s_a + base;  // taps J-N .. J, ascending
         int* kr = s_k + base + (S % 2 == 0 ? (uint32_t)kEven : (uint32_t)(R.K0 - R.J + N));
 #pragma unroll
@@ -939,7 +954,7 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
 #pragma unroll
         for (int sl = 0; sl < S; ++sl) atomicAdd(kr + sl, fixed_round(svkr, R.g[sl]));
         if (++jj == cnt) jj = 0;
-    }
+    } while (jj != jstart);
 }
 
 // Box spline: the row weights psi(X - i) = F_{i-i0} - F_{i-i0+1} of the
@@ -950,7 +965,9 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
                                     int W, int* s_a)
 {
     int jj = (int)((((threadIdx.x * 13u) & 255u) * (unsigned)cnt) >> 8);
-    for (int c = 0; c < cnt; ++c) {
+    // every row once, from jj round to jj (cnt >= 1)
+    const int jstart = jj;
+    do {
         // q > 0 (halo-relative column), so truncation is the floor
         const double q = fma(kap, (double)jj, q0);
         const float t = (float)__builtin_amdgcn_fract(q);
@@ -971,7 +988,7 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
             atomicAdd(ar + 2, fixed_round(svs, F));
         }
         if (++jj == cnt) jj = 0;
-    }
+    } while (jj != jstart);
 }
 
 __device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, float sv, int e, bool vert, int maj0,
