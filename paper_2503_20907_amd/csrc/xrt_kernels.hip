@@ -578,9 +578,10 @@ struct FwdArgs {
 };
 
 // Sum over the rows [ja, jb] of one line (times tap_scale<N>).  C and D are
-// the layout bases (uniform); element (row j, minor i) sits at
-// j * pitch + kPad + i, and q is X + (n+1)/2 + kPad at row ja (the padded
-// column coordinate, positive on every row a line reaches).
+// the layout bases (uniform) at row 0 of the row numbers ja, jb; element
+// (row j, minor i) sits at j * pitch + kPad + i, and q is X + (n+1)/2 + kPad
+// at row ja (the padded column coordinate, positive on every row a line
+// reaches).
 template <int N, int S>
 __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const LineConst& lc,
                                  const float4* __restrict__ tab, const float* __restrict__ C,
@@ -588,8 +589,8 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
 {
     const float rho = lc.rho;
     const float ern = tap_scale<N>() * lc.rn;
-    // byte offsets (the layouts are below 4 GiB), so that the loads take the
-    // uniform base plus a 32-bit offset
+    // byte offsets (within one strip), so that the loads take the uniform
+    // base plus a 32-bit offset
     const char* __restrict__ Cb = (const char*)C;
     const char* __restrict__ Db = (const char*)D;
     uint32_t off = (uint32_t)ja * (uint32_t)pitch * 4u;
@@ -657,8 +658,11 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
     const double xc = A.xc[k], kap = A.kap[k];
     const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
     const int pitch = VERT ? A.pitch_v : A.pitch_h;
-    const float* __restrict__ C = VERT ? A.cv : A.ch;
-    const float* __restrict__ D = VERT ? A.dv : A.dh;
+    // layout bases at the strip's first row, so that the walks' 32-bit byte
+    // offsets stay within one strip (a whole layout can exceed 4 GiB)
+    const int r0 = strip * kStrip;
+    const float* __restrict__ C = (VERT ? A.cv : A.ch) + (size_t)r0 * (size_t)pitch;
+    const float* __restrict__ D = (VERT ? A.dv : A.dh) + (size_t)r0 * (size_t)pitch;
     const double x0 = xc - kap * (0.5 * (nmaj - 1));
     float acc = 0.f;
     int ja, jb;
@@ -672,8 +676,8 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
         const bool neg = __ballot(ja <= jb && bk.neg) != 0ull;
         if (ja <= jb) {
             const double q0 = x0 + kap * (double)ja + (double)kPad;
-            acc = neg ? fwd_walk_box<true>(q0, kap, ja, jb, bk, C, pitch)
-                      : fwd_walk_box<false>(q0, kap, ja, jb, bk, C, pitch);
+            acc = neg ? fwd_walk_box<true>(q0, kap, ja - r0, jb - r0, bk, C, pitch)
+                      : fwd_walk_box<false>(q0, kap, ja - r0, jb - r0, bk, C, pitch);
         }
     } else {
         const double H = 0.5 * (N + 1);
@@ -685,10 +689,10 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
         const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
         if (ja <= jb) {
             const double q0 = x0 + kap * (double)ja + H + (double)kPad;
-            if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-            else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-            else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
-            else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja, jb, lc, s_tab, C, D, pitch);
+            if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
+            else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
+            else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
+            else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
         }
     }
     *ja_out = ja;
