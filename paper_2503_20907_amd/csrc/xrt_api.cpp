@@ -16,6 +16,11 @@ namespace {
 
 constexpr uint64_t kPlanMagic = 0x58525450'4c414e31ull;  // "XRTPLAN1"
 constexpr int kMaxGrid = 32768;
+// persistent forward: at most this many bytes of per-strip line sums, and
+// workgroups per compute unit (measured on the 2048^2 benchmark: 8 per CU and
+// 512 lines per item beat 2, 4 or 16 per CU and 256-2048 lines)
+constexpr size_t kMaxStripSums = (size_t)4 << 30;
+constexpr int kFwdBlocksPerCU = 8;
 
 thread_local char g_last_error[256] = "";
 
@@ -140,7 +145,7 @@ struct Allocs {
 void free_plan_memory(xrt_plan* p, hipStream_t s)
 {
     void* ptrs[] = {p->xc, p->kap, p->idx, p->off, p->hdr, p->tab,
-                    p->cv, p->dv, p->ch, p->dh, p->sw, p->part, p->adj_part};
+                    p->cv, p->dv, p->ch, p->dh, p->sw, p->part, p->spart, p->fctr, p->adj_part};
     for (void* q : ptrs)
         if (q) (void)hipFreeAsync(q, s);
 }
@@ -180,6 +185,15 @@ const char* xrt_last_error(void) { return g_last_error; }
 
 xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream,
                            xrt_plan** out)
+{
+    return xrt::plan_create(g, degree, lines, stream, true, out);
+}
+
+}  // extern "C"
+
+namespace xrt {
+xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool fwd_buffers,
+                       xrt_plan** out)
 {
     if (!out) return XRT_EINVAL;
     *out = nullptr;
@@ -227,15 +241,29 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     p->ch = al.get<float>((size_t)g.nx * p->pitch_h);
     p->dh = al.get<float>((size_t)g.nx * p->pitch_h);
     p->sw = al.get<float>(m);
-    // Small grids: one orientation's layouts fit in L2, so all its strips can
-    // run in one launch (more lines in flight) with a partial sum per strip.
-    // Large grids keep the strip-by-strip schedule and one running sum.
+    // The forward runs as one persistent launch with a sum per line and strip
+    // (summed in strip order afterwards) while those sums take at most
+    // kMaxStripSums bytes; beyond that, one launch per strip adds into one
+    // running sum per line.  Plans inside a batch need neither (the batch
+    // has its own forward).
     {
         const int ns = std::max(p->strips_v, p->strips_h);
-        const size_t lay = (size_t)std::max((int64_t)g.ny * p->pitch_v, (int64_t)g.nx * p->pitch_h) * 2 * sizeof(float);
-        p->fwd_conc = (ns > 1 && lay <= ((size_t)4 << 20) && (size_t)ns * (size_t)m * sizeof(double) <= ((size_t)256 << 20))
-                          ? 1 : 0;
-        p->part = al.get<double>(p->fwd_conc ? (size_t)ns * m : (size_t)m);
+        const size_t sums = (size_t)ns * (size_t)m * sizeof(float);
+        p->fwd_persist = fwd_buffers && sums <= kMaxStripSums ? 1 : 0;
+        if (p->fwd_persist) {
+            p->spart = al.get<float>((size_t)ns * (size_t)m);
+            p->fctr = al.get<unsigned int>(1);
+            int dev = 0, cus = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+                cus = 256;
+            p->fwd_grid = cus * kFwdBlocksPerCU;
+            // two lines per thread and item, unless that leaves fewer than
+            // four items per workgroup (small problems: one line per thread)
+            p->fwd_lpi = (int64_t)ns * (m / (2 * kBlock)) >= 4 * (int64_t)p->fwd_grid ? 2 * kBlock : kBlock;
+        } else {
+            p->part = al.get<double>((size_t)m);
+        }
         // few adjoint tiles: split each tile's candidate lines over several
         // workgroups (partial images, summed in a fixed order)
         const int64_t tiles = (int64_t)((g.nx + kTileI - 1) / kTileI) * ((g.ny + kTileJ - 1) / kTileJ);
@@ -336,6 +364,9 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
     *out = p;
     return XRT_OK;
 }
+}  // namespace xrt
+
+extern "C" {
 
 static bool plan_ok(const xrt_plan* p) { return p && p->magic == kPlanMagic; }
 

@@ -181,7 +181,7 @@ xrt_status xrt_batch_create(const xrt_problem* problems, int32_t count, void* st
     b->cfg.pad = 0;
     for (int p = 0; p < count; ++p) {
         xrt_plan* pl = nullptr;
-        xrt_status st = xrt_plan_create(problems[p].grid, problems[p].degree, &problems[p].lines, stream, &pl);
+        xrt_status st = xrt::plan_create(problems[p].grid, problems[p].degree, &problems[p].lines, stream, false, &pl);
         if (st != XRT_OK) {
             release(b);
             delete b;

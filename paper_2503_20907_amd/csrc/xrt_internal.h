@@ -97,6 +97,11 @@ hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, h
 hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s);
 hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s);
 
+// xrt_plan_create; fwd_buffers = false leaves out the persistent forward's
+// buffers (plans inside a batch, which has its own forward)
+xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool fwd_buffers,
+                       xrt_plan** out);
+
 // batches of plans (persistent launches; see xrt_batch.cpp)
 size_t batch_prob_size();
 // strips of the forward schedule of a plan (per-strip partial sums: strips x lines floats)
@@ -151,9 +156,13 @@ struct xrt_plan {
     int pitch_v, pitch_h;
     float *cv, *dv, *ch, *dh;  // coefficient / difference layouts
     float* sw;                 // sinogram in sorted order, scaled
-    double* part;              // forward sums over strips: [m], or [strips][m] when fwd_conc
     int strips_v, strips_h;    // strips of kStrip rows, per orientation
-    int fwd_conc;              // 1: the strips of an orientation run in one launch
+    int fwd_persist;           // 1: one persistent forward launch (spart); 0: one launch per strip (part)
+    int fwd_grid;              // workgroups of the persistent launch
+    int fwd_lpi;               // lines per work item of the persistent launch
+    double* part;              // [m] running sums over the strips (fwd_persist = 0)
+    float* spart;              // [max strips][m] per-strip sums (fwd_persist = 1)
+    unsigned int* fctr;        // work counter of the persistent launch
     int adj_split;             // workgroups sharing one adjoint tile's candidate lines
     float* adj_part;           // [adj_split][ny][nx] partial images (adj_split > 1)
 };

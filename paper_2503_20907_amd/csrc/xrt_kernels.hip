@@ -570,12 +570,16 @@ struct FwdArgs {
     int nx, ny;
     double h;
     float* sino;
-    double* part;  // [m] sums over the strips done so far, or [strips][m] (concurrent)
+    double* part;            // [m] sums over the strips done so far (one launch per strip)
+    float* spart;            // [strips][m] per-strip sums (persistent launch)
+    unsigned int* counter;   // work counter of the persistent launch
+    int persist;             // 1: persistent launch (spart), 0: one launch per strip (part)
+    int lines_per_item;      // persistent launch: lines per work item (a multiple of kBlock)
     int strips_v, strips_h;
-    int strip;     // strip of this launch (sequential schedule)
-    int concurrent;  // 1: blockIdx.x / nblk_pad is the strip; each strip writes its own partials
+    int strip;     // strip of this launch (one launch per strip)
     int nblk, nblk_pad;
 };
+
 
 // Sum over the rows [ja, jb] of one line (times tap_scale<N>).  C and D are
 // the layout bases (uniform) at row 0 of the row numbers ja, jb; element
@@ -704,7 +708,8 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
 // flight at any time read one strip of the layout, which stays in L2.  The
 // launches of one orientation run in strip order and each adds its partial
 // sums into part[k] (the first one writes), so the sum is deterministic;
-// k_fwd_reduce scales and scatters.
+// k_fwd_reduce scales and scatters.  Used when the persistent launch's
+// per-strip sums would take too much memory.
 template <int N, bool VERT>
 __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
 {
@@ -715,13 +720,8 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
         __syncthreads();
     }
 
-    int strip = A.strip;
-    int bid = blockIdx.x;
-    if (A.concurrent) {
-        strip = blockIdx.x / A.nblk_pad;
-        bid = blockIdx.x - strip * A.nblk_pad;
-        if (strip >= (VERT ? A.strips_v : A.strips_h)) return;
-    }
+    const int strip = A.strip;
+    const int bid = blockIdx.x;
     const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
     // vertical lines are the sorted range [0, m_vert), horizontal ones
     // [m_vert, m_valid).  The grid covers all m lines; the blocks of this
@@ -736,9 +736,58 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     if (k >= end) return;
     int ja, jb;
     const float acc = fwd_strip_sum<N, VERT>(A, k, strip, s_tab, &ja, &jb);
-    if (A.concurrent) A.part[(int64_t)strip * A.m + k] = (double)acc;
-    else if (strip == 0) A.part[k] = (double)acc;
+    if (strip == 0) A.part[k] = (double)acc;
     else if (ja <= jb) A.part[k] += (double)acc;
+}
+
+__device__ inline int next_item(unsigned int* counter, int* s_item)
+{
+    __syncthreads();   // everyone is done with the previous item (and with *s_item)
+    if (threadIdx.x == 0) *s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    return *s_item;
+}
+
+// Forward as one persistent launch: workgroups take items (orientation,
+// strip, run of lines_per_item lines) from a counter, the vertical lines'
+// strips first, each orientation's strips in order, so that the workgroups
+// in flight read about one strip of the layouts (as with one launch per
+// strip, without a launch's tail per strip).  Line k's sum over strip st goes
+// to spart[st][k]; k_fwd_reduce adds the strips in order.  The counter starts
+// at zero; every workgroup leaves once the items are used up.
+template <int N>
+__global__ void __launch_bounds__(kBlock) k_forward_persist(FwdArgs A)
+{
+    __shared__ float4 s_tab[kTabMax];
+    __shared__ int s_item;
+    if constexpr (N != kBox3) {
+        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
+        for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
+    }
+    const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
+    const int lpi = A.lines_per_item;
+    const int64_t nbv = (m_vert + lpi - 1) / lpi;
+    const int64_t nbh = (m_valid - m_vert + lpi - 1) / lpi;
+    const int64_t items_v = nbv * A.strips_v, items = items_v + nbh * A.strips_h;
+    for (;;) {
+        const int it = next_item(A.counter, &s_item);  // synchronises (also after the table load)
+        if (it >= items) break;
+        const bool vert = it < items_v;   // uniform over the workgroup
+        const int64_t li = vert ? it : it - items_v;
+        const int64_t nb = vert ? nbv : nbh;
+        const int st = (int)(li / nb);
+        const int64_t first = (vert ? 0 : m_vert) + (li - st * nb) * lpi;
+        const int64_t end = vert ? m_vert : m_valid;
+        for (int sub = 0; sub < lpi; sub += kBlock) {
+            const int64_t k = first + sub + threadIdx.x;
+            if (k < end) {
+                int ja, jb;
+                const float acc = vert ? fwd_strip_sum<N, true>(A, k, st, s_tab, &ja, &jb)
+                                       : fwd_strip_sum<N, false>(A, k, st, s_tab, &ja, &jb);
+                A.spart[(int64_t)st * A.m + k] = acc;
+            }
+        }
+    }
 }
 
 // sino[idx[k]] = (sum over strips of part[s][k]) * h / max(|cos|,|sin|);
@@ -751,10 +800,14 @@ __global__ void __launch_bounds__(kBlock) k_fwd_reduce(FwdArgs A)
     const int64_t m_valid = A.hdr->m_valid;
     float v = 0.f;
     if (k < m_valid) {
-        double acc = A.part[k];
-        if (A.concurrent) {
+        double acc;
+        if (A.persist) {
+            // the strip sums in strip order, as the launches per strip add them
             const int ns = k < A.hdr->m_vert ? A.strips_v : A.strips_h;
-            for (int st = 1; st < ns; ++st) acc += A.part[(int64_t)st * A.m + k];
+            acc = (double)A.spart[k];
+            for (int st = 1; st < ns; ++st) acc += (double)A.spart[(int64_t)st * A.m + k];
+        } else {
+            acc = A.part[k];
         }
         const double kap = A.kap[k];
         v = (float)(acc * A.h * sqrt(1.0 + kap * kap) / (double)tap_scale<N>());
@@ -1354,14 +1407,6 @@ __device__ inline void fwd_block_any(const BatchProb& P, int64_t k0, int st, con
     else if (k < P.m_valid) fwd_line_strip<N, false>(P, k, st, s_tab);
 }
 
-__device__ inline int next_item(unsigned int* counter, int* s_item)
-{
-    __syncthreads();   // everyone is done with the previous item (and with *s_item)
-    if (threadIdx.x == 0) *s_item = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    return *s_item;
-}
-
 // items (problem, strip * blocks + block): the items of one problem are
 // listed strip by strip, so the workgroups in flight share one strip of its
 // layouts (as in the single-problem schedule)
@@ -1591,10 +1636,13 @@ static FwdArgs make_fwd_args(const xrt_plan* p, float* sino)
     a.h = p->g.h;
     a.sino = sino;
     a.part = p->part;
+    a.spart = p->spart;
+    a.counter = p->fctr;
+    a.persist = p->fwd_persist;
+    a.lines_per_item = p->fwd_lpi;
     a.strips_v = p->strips_v;
     a.strips_h = p->strips_h;
     a.strip = 0;
-    a.concurrent = 0;
     a.nblk = (int)((p->m + kBlock - 1) / kBlock);
     a.nblk_pad = (a.nblk + 7) / 8 * 8;
     return a;
@@ -1630,21 +1678,18 @@ template <int N>
 static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
 {
     FwdArgs a = make_fwd_args(p, sino);
-    // the split between vertical and horizontal lines is known on the device
-    // only: the grid of each launch covers all m lines and blocks past the
-    // launch's range return at once
-    a.concurrent = p->fwd_conc;
-    a.strip = 0;
-    if (p->fwd_conc) {
-        hipLaunchKernelGGL((k_forward<N, true>), dim3((unsigned)(a.nblk_pad * p->strips_v)), dim3(kBlock), 0, s, a);
-        hipError_t e = hipGetLastError();
+    if (p->fwd_persist) {
+        hipError_t e = launch_reset_counters(p->fctr, 1, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_forward<N, false>), dim3((unsigned)(a.nblk_pad * p->strips_h)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_forward_persist<N>, dim3((unsigned)p->fwd_grid), dim3(kBlock), 0, s, a);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_fwd_reduce<N>, dim3((unsigned)a.nblk), dim3(kBlock), 0, s, a);
         return hipGetLastError();
     }
+    // the split between vertical and horizontal lines is known on the device
+    // only: the grid of each launch covers all m lines and blocks past the
+    // launch's range return at once
     const int ns = p->strips_v > p->strips_h ? p->strips_v : p->strips_h;
     for (int st = 0; st < ns; ++st) {
         a.strip = st;
