@@ -338,10 +338,10 @@ def main():
     achieved = nnz * F / t_dom / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": measured_traffic("k_adjoint<" if dominant == "adjoint" else "k_forward<"),
+                "traffic": measured_traffic("k_adjoint<" if dominant == "adjoint" else "k_forward_persist<"),
                 "kernel": ("adjoint: k_sort_sino + k_adjoint<3, 1> (vertical lines) + k_adjoint<3, 2> "
                            "(horizontal lines), timed as one call" if dominant == "adjoint" else
-                           "forward: k_layout_v/h + k_forward strip launches + k_fwd_reduce, timed as one call"),
+                           "forward: k_layout_v/h + k_forward_persist + k_fwd_reduce, timed as one call"),
                 "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                 "work": f"nnz(H) = {nnz} basis evaluations x {F} flops per launch"}
 
