@@ -36,16 +36,29 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 G
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_source_hash(path: str) -> str:
-    """SHA-256 (first 16 hex digits) of a source file with its comments and
-    whitespace removed: it changes when the code does, not when a comment does."""
+# The sources that decide what the profiled kernels do: their code and their
+# launch configuration (tile split, grid sizes, layouts).
+KERNEL_SOURCES = ("xrt_kernels.hip", "xrt_api.cpp", "xrt_internal.h")
+
+
+def kernel_source_hash(paths=None) -> str:
+    """SHA-256 (first 16 hex digits) of the kernel sources (KERNEL_SOURCES by
+    default) with comments and whitespace removed: it changes when the code or
+    a launch configuration does, not when a comment does."""
     import hashlib
     import re
-    text = open(path, encoding="utf-8").read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", "", text)
-    text = re.sub(r"\s+", "", text)
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+    if paths is None:
+        paths = [os.path.join(ROOT, "paper_2503_20907_amd", "csrc", f) for f in KERNEL_SOURCES]
+    elif isinstance(paths, str):
+        paths = [paths]
+    h = hashlib.sha256()
+    for path in paths:
+        text = open(path, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"\s+", "", text)
+        h.update(text.encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
@@ -54,11 +67,11 @@ def measured_traffic(kernel: str):
     the kernel source changed since the counters were taken."""
     import hashlib
     import re
-    src = os.path.join(ROOT, "paper_2503_20907_amd", "csrc", "xrt_kernels.hip")
+    srcs = [os.path.join(ROOT, "paper_2503_20907_amd", "csrc", f) for f in KERNEL_SOURCES]
     summ = os.path.join(ROOT, "profiles", "hbm_traffic_2048_cubic_fan_random.md")
-    if not (os.path.exists(src) and os.path.exists(summ)):
+    if not (all(os.path.exists(f) for f in srcs) and os.path.exists(summ)):
         return None
-    sha = kernel_source_hash(src)
+    sha = kernel_source_hash(srcs)
     total = 0
     found = False
     for line in open(summ):
@@ -340,7 +353,8 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
                 "traffic": measured_traffic("k_adjoint<" if dominant == "adjoint" else "k_forward_persist<"),
                 "kernel": ("adjoint: k_sort_sino + k_adjoint<3, 1> (vertical lines) + k_adjoint<3, 2> "
-                           "(horizontal lines), timed as one call" if dominant == "adjoint" else
+                           "(horizontal lines) + k_adj_reduce after each, timed as one call"
+                           if dominant == "adjoint" else
                            "forward: k_layout_v/h + k_forward_persist + k_fwd_reduce, timed as one call"),
                 "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                 "work": f"nnz(H) = {nnz} basis evaluations x {F} flops per launch"}

@@ -21,6 +21,8 @@ constexpr int kMaxGrid = 32768;
 // 512 lines per item beat 2, 4 or 16 per CU and 256-2048 lines)
 constexpr size_t kMaxStripSums = (size_t)4 << 30;
 constexpr int kFwdBlocksPerCU = 8;
+// adjoint workgroups per orientation pass that the tile split aims at
+constexpr int64_t kAdjUnits = 12288;
 
 thread_local char g_last_error[256] = "";
 
@@ -192,7 +194,7 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
 }  // extern "C"
 
 namespace xrt {
-xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool fwd_buffers,
+xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool own_buffers,
                        xrt_plan** out)
 {
     if (!out) return XRT_EINVAL;
@@ -245,11 +247,11 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     // (summed in strip order afterwards) while those sums take at most
     // kMaxStripSums bytes; beyond that, one launch per strip adds into one
     // running sum per line.  Plans inside a batch need neither (the batch
-    // has its own forward).
+    // has its own forward and adjoint launches).
     {
         const int ns = std::max(p->strips_v, p->strips_h);
         const size_t sums = (size_t)ns * (size_t)m * sizeof(float);
-        p->fwd_persist = fwd_buffers && sums <= kMaxStripSums ? 1 : 0;
+        p->fwd_persist = own_buffers && sums <= kMaxStripSums ? 1 : 0;
         if (p->fwd_persist) {
             p->spart = al.get<float>((size_t)ns * (size_t)m);
             p->fctr = al.get<unsigned int>(1);
@@ -261,13 +263,16 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
             // two lines per thread and item, unless that leaves fewer than
             // four items per workgroup (small problems: one line per thread)
             p->fwd_lpi = (int64_t)ns * (m / (2 * kBlock)) >= 4 * (int64_t)p->fwd_grid ? 2 * kBlock : kBlock;
-        } else {
+        } else if (own_buffers) {
             p->part = al.get<double>((size_t)m);
         }
-        // few adjoint tiles: split each tile's candidate lines over several
-        // workgroups (partial images, summed in a fixed order)
+        // split each adjoint tile's candidate lines over up to 8 workgroups
+        // (partial images, summed in a fixed order), aiming at kAdjUnits
+        // workgroups per pass: with few units per compute unit the tiles that
+        // finish last leave it partly idle (2048^2: 2048 tiles per pass, cubic
+        // adjoint 27.9 ms unsplit, 25.4 ms split 6 ways)
         const int64_t tiles = (int64_t)((g.nx + kTileI - 1) / kTileI) * ((g.ny + kTileJ - 1) / kTileJ);
-        p->adj_split = tiles >= 1024 ? 1 : (int)std::min<int64_t>(8, (1024 + tiles - 1) / tiles);
+        p->adj_split = own_buffers ? (int)std::min<int64_t>(8, (kAdjUnits + tiles - 1) / tiles) : 1;
         p->adj_part = p->adj_split > 1 ? al.get<float>((size_t)p->adj_split * g.nx * g.ny) : nullptr;
     }
     // temporaries

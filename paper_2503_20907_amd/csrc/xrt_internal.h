@@ -97,9 +97,10 @@ hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, h
 hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s);
 hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s);
 
-// xrt_plan_create; fwd_buffers = false leaves out the persistent forward's
-// buffers (plans inside a batch, which has its own forward)
-xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool fwd_buffers,
+// xrt_plan_create; own_buffers = false leaves out the buffers that only the
+// plan's own forward and adjoint use (persistent forward sums, split-tile
+// partial images): plans inside a batch, which has its own launches
+xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool own_buffers,
                        xrt_plan** out);
 
 // batches of plans (persistent launches; see xrt_batch.cpp)
