@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -249,9 +250,14 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     // running sum per line.  Plans inside a batch need neither (the batch
     // has its own forward and adjoint launches).
     {
+        // test hook: XRT_SCHEDULE=plain selects the schedules otherwise kept
+        // for very large problems (one forward launch per strip, unsplit
+        // adjoint tiles), so that tests can compare them with the defaults
+        const char* sched = getenv("XRT_SCHEDULE");
+        const bool plain = sched && strcmp(sched, "plain") == 0;
         const int ns = std::max(p->strips_v, p->strips_h);
         const size_t sums = (size_t)ns * (size_t)m * sizeof(float);
-        p->fwd_persist = own_buffers && sums <= kMaxStripSums ? 1 : 0;
+        p->fwd_persist = own_buffers && !plain && sums <= kMaxStripSums ? 1 : 0;
         if (p->fwd_persist) {
             p->spart = al.get<float>((size_t)ns * (size_t)m);
             p->fctr = al.get<unsigned int>(1);
@@ -272,7 +278,7 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
         // finish last leave it partly idle (2048^2: 2048 tiles per pass, cubic
         // adjoint 27.9 ms unsplit, 25.4 ms split 6 ways)
         const int64_t tiles = (int64_t)((g.nx + kTileI - 1) / kTileI) * ((g.ny + kTileJ - 1) / kTileJ);
-        p->adj_split = own_buffers ? (int)std::min<int64_t>(8, (kAdjUnits + tiles - 1) / tiles) : 1;
+        p->adj_split = own_buffers && !plain ? (int)std::min<int64_t>(8, (kAdjUnits + tiles - 1) / tiles) : 1;
         p->adj_part = p->adj_split > 1 ? al.get<float>((size_t)p->adj_split * g.nx * g.ny) : nullptr;
     }
     // temporaries

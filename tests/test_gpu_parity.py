@@ -309,3 +309,35 @@ def test_large_sampled_box_spline(orc, torch, ops):
     rhs = float(np.dot(coeffs.astype(np.float64).ravel(), got_a.astype(np.float64)))
     assert abs(lhs - rhs) <= TOL * abs(lhs)
     plan.close()
+
+
+# ------------------------------------------- schedules kept for large problems
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 16])
+def test_plain_schedules_match_defaults(torch, ops, n):
+    """The forward's one launch per strip (used when the per-strip sums of
+    the persistent launch would exceed its memory cap) gives the same
+    sinogram bit for bit: both add the strip sums in strip order.  Unsplit
+    adjoint tiles (used on grids with very many tiles) agree with split ones
+    to FP32 rounding: only the order of the partial images' sums differs."""
+    import os
+    say(f"case: plain vs default schedules, basis {n}")
+    rng = np.random.default_rng(900 + n)
+    m = 30000
+    th = rng.uniform(0, math.pi, m).astype(np.float32)
+    y = rng.uniform(-190, 190, m).astype(np.float32)
+    lines = ops.Lines(theta=th, y=y)
+    c = to_dev(torch, rng.normal(size=(290, 330)))
+    s = to_dev(torch, rng.normal(size=m))
+    fwd, adj = [], []
+    for sched in ("default", "plain"):
+        if sched == "plain":
+            os.environ["XRT_SCHEDULE"] = "plain"
+        try:
+            plan = ops.Plan(330, 290, n, lines)
+        finally:
+            os.environ.pop("XRT_SCHEDULE", None)
+        fwd.append(plan.forward(c).cpu().numpy())
+        adj.append(plan.adjoint(s).cpu().numpy())
+        plan.close()
+    assert np.array_equal(fwd[0], fwd[1])
+    assert rel_l2(adj[0], adj[1]) < 1e-6
