@@ -985,8 +985,10 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
 {
     // start each lane at a different row (spread over [0, cnt) by a
     // multiply and shift) so that the lanes of a wave rarely update the same
-    // LDS word in one instruction
-    int jj = (int)((((threadIdx.x * 13u) & 255u) * (unsigned)cnt) >> 8);
+    // LDS word in one instruction.  The lane index is scrambled (37 l mod 64):
+    // neighbouring lanes hold neighbouring lines, and giving them neighbouring
+    // rows (l cnt / 64) took 33 ms instead of 25 (2048^2 cubic adjoint).
+    int jj = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
     const float svkr = svk * lc.rn;
     const TapScaled<N> tk = tap_scaled<N>(svs, lc.rho);
     // knot slots start at K0 = J + o, o = 1 - S/2 for even S (a constant), so
@@ -1021,7 +1023,8 @@ template <bool NEG>
 __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, float svs, const BoxRow& bk,
                                     int W, int* s_a)
 {
-    int jj = (int)((((threadIdx.x * 13u) & 255u) * (unsigned)cnt) >> 8);
+    // start row spread as in adj_walk
+    int jj = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
     // every row once, from jj round to jj (cnt >= 1)
     const int jstart = jj;
     do {
