@@ -109,7 +109,12 @@ xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xr
                        float* coeffs_out, void* stream);
 
 /* Builds a plan for (grid, degree, lines).  The line arrays are read during
- * the call only.  On error *out is NULL and nothing stays allocated. */
+ * the call only.  On error *out is NULL and nothing stays allocated.
+ * Device memory held by the plan: about 24 B per line (sorted line records,
+ * scaled sinogram), 4 B per line and strip of 128 grid rows (the forward's
+ * strip sums; 8 B per line instead when that would pass 4 GiB), four padded
+ * copies of the coefficient grid, up to 8 partial images, and 4 B per
+ * (orientation, slope bin, crossing bucket) key. */
 xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream,
                            xrt_plan** out);
 

@@ -31,7 +31,13 @@
 // every line adds W_d s to the cells J-d and r^n E(.) s to the knots K of an
 // LDS tile, and the tile's output is A + Delta^T K.  One launch takes the
 // vertical lines and writes the image, a second one the horizontal lines and
-// adds into it; each tile's pixels are written by one workgroup per launch.
+// adds into it.  A tile's candidate lines are shared by up to 8 workgroups
+// (every split-th chunk each), whose partial images k_adj_reduce adds in a
+// fixed order.
+//
+// The forward is one persistent launch: workgroups take (orientation, strip,
+// run of lines) items in strip order, and each line's strip sums are added
+// in strip order afterwards (k_fwd_reduce).
 //
 // The 3-directional box spline (basis code kBox3) uses the same schedules
 // with its own row arithmetic (box_row, box_F): a telescoped row sum over two
