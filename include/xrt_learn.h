@@ -194,6 +194,43 @@ xrt_status xrt_solve_ex(const xrt_plan* plan, float lambda, const float* b, floa
                         xrt_unet* net, const xrt_solve_opts* opts, xrt_solve_info* info, double* history,
                         int32_t history_cap, void* stream);
 
+/* ------------------------------------- sinogram-domain filter preconditioner
+ * For line lists made of n_views consecutive runs of n_bins lines (one view
+ * each, neighbouring bins neighbouring lines, as parallel- and fan-beam
+ * sinograms are), the preconditioner
+ *     P r = H^T (f * (H r)) + mu r,
+ * f a centred filter of `taps` (odd) coefficients applied along each view.
+ * With f a positive combination of second differences and mu >= 0, P is
+ * symmetric positive semi-definite (definite if mu > 0).  The filter's
+ * coefficients are fitted from training pairs (paper_2503_20907_amd.learn). */
+
+/* out[v][j] = sum_k filter[k] sino[v][j + k - taps/2] for v < n_views,
+ * j < n_bins (zero outside a view).  All pointers are device memory; sino
+ * and out [n_views][n_bins] must not overlap.  Errors: EINVAL (null pointer,
+ * n_views < 0, n_bins < 1, taps even or outside [1, 63]). */
+xrt_status xrt_sino_filter(const float* sino, int64_t n_views, int32_t n_bins, const float* filter, int32_t taps,
+                           float* out, void* stream);
+
+typedef struct {
+    int64_t n_views;       /* the plan's lines: n_views runs of n_bins lines */
+    int32_t n_bins;
+    int32_t taps;          /* odd, 1..63 */
+    const float* filter;   /* device, taps floats, centred */
+    float mu;              /* >= 0 */
+    int32_t pad;
+} xrt_sino_precond;
+
+/* Preconditioned CG (Hestenes-Stiefel with z_k = P r_k, P as above) for
+ * (H^T H + lambda L^T L) x = b from x = 0; stopping, confirmation, history
+ * and x as for xrt_solve.  info->learned_accepted counts the applications of
+ * P (one per step; each costs one forward and one adjoint of the plan).
+ * Errors: EPLAN, EINVAL (null pc or filter, taps even or outside [1, 63],
+ * mu negative or not finite, n_views * n_bins different from the plan's
+ * line count, tol <= 0, maxit < 0). */
+xrt_status xrt_solve_sino_pcg(const xrt_plan* plan, float lambda, const float* b, float* x, float tol,
+                              int32_t maxit, const xrt_sino_precond* pc, xrt_solve_info* info, double* history,
+                              int32_t history_cap, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

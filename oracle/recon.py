@@ -15,7 +15,8 @@ What it computes:
   Neumann boundary (no difference across the edge), so the minimiser solves
   the normal equations ``(H^T H + lambda L^T L) c = H^T p``.
 * Conjugate gradients (Hestenes-Stiefel), the solver the paper runs on this
-  problem (Section IV-B, "conjugate-gradient descent").
+  problem (Section IV-B), and its preconditioned form with the sinogram-domain
+  filter preconditioner ``P r = H^T (f * (H r)) + mu r`` (not in the paper).
 * A small U-Net acting on a residual image (the learned preconditioner), its
   loss and its exact gradient by explicit back-propagation, and one Adam step
   (Kingma and Ba, 2015).  None of this is in the paper; the architecture is
@@ -90,6 +91,62 @@ def cg(apply, b, tol=1e-3, maxit=1000, x0=None):
         it += 1
         hist.append(np.sqrt(rr) / bn)
     return x, it, hist
+
+
+def pcg(apply, precond, b, tol=1e-3, maxit=1000):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel with z = P r) on an
+    SPD operator with an SPD (or semi-definite) preconditioner ``precond``.
+
+    Stops when ||b - A x|| <= tol ||b|| with the recursively updated residual.
+    Returns (x, iterations, list of relative residual norms).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = precond(r)
+    p = z.copy()
+    rz = float(np.vdot(r, z))
+    bn = float(np.sqrt(np.vdot(b, b)))
+    hist = [1.0]
+    it = 0
+    while hist[-1] > tol and it < maxit:
+        q = apply(p)
+        alpha = rz / float(np.vdot(p, q))
+        x = x + alpha * p
+        r = r - alpha * q
+        z = precond(r)
+        rz_new = float(np.vdot(r, z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        it += 1
+        hist.append(float(np.sqrt(np.vdot(r, r))) / bn)
+    return x, it, hist
+
+
+def sino_filter(s, n_views, n_bins, f):
+    """out[v][j] = sum_k f[k] s[v][j + k - K//2] along each of the n_views
+    runs of n_bins samples, zero outside a run (K = len(f) odd)."""
+    s = np.asarray(s, dtype=np.float64).reshape(n_views, n_bins)
+    f = np.asarray(f, dtype=np.float64)
+    h = len(f) // 2
+    out = np.zeros_like(s)
+    for v in range(n_views):
+        for j in range(n_bins):
+            acc = 0.0
+            for k in range(len(f)):
+                jj = j + k - h
+                if 0 <= jj < n_bins:
+                    acc += f[k] * s[v, jj]
+            out[v, j] = acc
+    return out.ravel()
+
+
+def sino_precondition(n, r, line_cs, f, mu, n_views, n_bins, spacing=1.0, cx=0.0, cy=0.0):
+    """P r = H^T (f * (H r)) + mu r with the oracle's forward and adjoint."""
+    r = np.asarray(r, dtype=np.float64)
+    ny, nx = r.shape
+    s = sino_filter(_forward(n, r, line_cs, spacing, cx, cy), n_views, n_bins, f)
+    return _adjoint(n, s, line_cs, nx, ny, spacing, cx, cy) + mu * r
 
 
 # ---------------------------------------------------------------------------

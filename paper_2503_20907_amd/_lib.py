@@ -38,7 +38,8 @@ EXPORTS = (
     "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_set_gain", "xrt_unet_get_gain",
     "xrt_unet_set_relu", "xrt_unet_apply", "xrt_unet_loss_grad", "xrt_unet_train_step",
     "xrt_unet_loss_grad_normal", "xrt_unet_train_step_normal", "xrt_conv3x3_forward",
-    "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve", "xrt_solve_ex",
+    "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve", "xrt_solve_ex", "xrt_sino_filter",
+    "xrt_solve_sino_pcg",
     # xrt_batch.h
     "xrt_batch_create", "xrt_batch_destroy", "xrt_batch_buffers", "xrt_batch_info", "xrt_batch_forward",
     "xrt_batch_adjoint", "xrt_batch_run", "xrt_batch_get_config", "xrt_batch_set_config",
@@ -67,6 +68,11 @@ class XrtSolveInfo(ctypes.Structure):
 class XrtSolveOpts(ctypes.Structure):
     _fields_ = [("window", ctypes.c_int32), ("period", ctypes.c_int32), ("net_steps", ctypes.c_int32),
                 ("restart", ctypes.c_int32)]
+
+
+class XrtSinoPrecond(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int64), ("n_bins", ctypes.c_int32), ("taps", ctypes.c_int32),
+                ("filter", ctypes.c_void_p), ("mu", ctypes.c_float), ("pad", ctypes.c_int32)]
 
 
 class XrtProblem(ctypes.Structure):
@@ -137,6 +143,9 @@ def load() -> ctypes.CDLL:
                               ctypes.POINTER(ctypes.c_double), i32, vp]
     lib.xrt_solve_ex.argtypes = [vp, f32, vp, vp, f32, i32, vp, ctypes.POINTER(XrtSolveOpts),
                                  ctypes.POINTER(XrtSolveInfo), ctypes.POINTER(ctypes.c_double), i32, vp]
+    lib.xrt_sino_filter.argtypes = [vp, i64, i32, vp, i32, vp, vp]
+    lib.xrt_solve_sino_pcg.argtypes = [vp, f32, vp, vp, f32, i32, ctypes.POINTER(XrtSinoPrecond),
+                                       ctypes.POINTER(XrtSolveInfo), ctypes.POINTER(ctypes.c_double), i32, vp]
     fpp = ctypes.POINTER(ctypes.c_void_p)
     lib.xrt_batch_create.argtypes = [ctypes.POINTER(XrtProblem), i32, vp, ctypes.POINTER(vp)]
     lib.xrt_batch_destroy.argtypes = [vp]
@@ -159,7 +168,7 @@ def load() -> ctypes.CDLL:
                  "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_apply",
                  "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
                  "xrt_unet_train_step_normal", "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve",
-                 "xrt_solve_ex"):
+                 "xrt_solve_ex", "xrt_sino_filter", "xrt_solve_sino_pcg"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -316,6 +325,20 @@ def xrt_solve_ex(plan, lam, b, x, tol, maxit, net, window, period, net_steps, re
     hist = (ctypes.c_double * max(1, int(history_cap)))()
     st = load().xrt_solve_ex(plan, float(lam), b, x, float(tol), int(maxit), net, ctypes.byref(opts),
                              ctypes.byref(info), hist if history_cap > 0 else None, int(history_cap), stream)
+    return st, info, [hist[i] for i in range(min(int(history_cap), info.iterations))]
+
+
+def xrt_sino_filter(sino, n_views, n_bins, filt, taps, out, stream) -> int:
+    return load().xrt_sino_filter(sino, int(n_views), int(n_bins), filt, int(taps), out, stream)
+
+
+def xrt_solve_sino_pcg(plan, lam, b, x, tol, maxit, n_views, n_bins, filt, taps, mu, history_cap, stream):
+    info = XrtSolveInfo()
+    pc = XrtSinoPrecond(int(n_views), int(n_bins), int(taps), filt, float(mu), 0)
+    hist = (ctypes.c_double * max(1, int(history_cap)))()
+    st = load().xrt_solve_sino_pcg(plan, float(lam), b, x, float(tol), int(maxit), ctypes.byref(pc),
+                                   ctypes.byref(info), hist if history_cap > 0 else None, int(history_cap),
+                                   stream)
     return st, info, [hist[i] for i in range(min(int(history_cap), info.iterations))]
 
 

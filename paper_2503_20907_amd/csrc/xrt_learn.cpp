@@ -895,4 +895,137 @@ done:
     return st;
 }
 
+static bool filter_ok(int32_t taps) { return taps >= 1 && taps <= 63 && taps % 2 == 1; }
+
+xrt_status xrt_sino_filter(const float* sino, int64_t n_views, int32_t n_bins, const float* filter, int32_t taps,
+                           float* out, void* stream)
+{
+    if (!sino || !filter || !out || n_views < 0 || n_bins < 1 || !filter_ok(taps)) return XRT_EINVAL;
+    XL_CHECK(xrl::sino_filter(sino, n_views, n_bins, filter, taps, out, (hipStream_t)stream), "sino_filter");
+    return XRT_OK;
+}
+
+// slots of the preconditioned CG (the S_* slots 5..7 are free in xrt_solve_ex's layout)
+enum { T_RZ = 5, T_RZN = 6, T_RRN = 7 };
+
+xrt_status xrt_solve_sino_pcg(const xrt_plan* plan, float lambda, const float* b, float* x, float tol,
+                              int32_t maxit, const xrt_sino_precond* pc, xrt_solve_info* info, double* history,
+                              int32_t history_cap, void* stream)
+{
+    int64_t m = 0, crossing = 0;
+    xrt_status st = xrt_plan_info(plan, &m, &crossing);
+    if (st != XRT_OK) return st;
+    if (!b || !x || !info || !pc || !pc->filter || !(tol > 0.f) || maxit < 0) return XRT_EINVAL;
+    if (!filter_ok(pc->taps) || !(pc->mu >= 0.f) || !isfinite(pc->mu)) return XRT_EINVAL;
+    if (pc->n_views < 0 || pc->n_bins < 1 || pc->n_views * (int64_t)pc->n_bins != m) return XRT_EINVAL;
+    memset(info, 0, sizeof(*info));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)plan->g.nx * plan->g.ny;
+    const int64_t ms = m > 0 ? m : 1;
+
+    // workspace: r, z, p, q; two sinograms; scalars
+    float* ws = nullptr;
+    double *slots = nullptr, *dpart = nullptr, *host = nullptr;
+    XL_CHECK(hipMallocAsync((void**)&ws, ((size_t)4 * n + 2 * (size_t)ms) * sizeof(float), s), "hipMallocAsync");
+    XL_CHECK(hipMallocAsync((void**)&slots, S_N * sizeof(double), s), "hipMallocAsync");
+    XL_CHECK(hipMallocAsync((void**)&dpart, (size_t)xrl::kMaxVecs * xrl::dots_parts() * sizeof(double), s),
+             "hipMallocAsync");
+    XL_CHECK(hipHostMalloc((void**)&host, S_N * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    float *r = ws, *z = ws + n, *p = ws + 2 * n, *q = ws + 3 * n, *sa = ws + 4 * n, *sb = sa + ms;
+
+    hipError_t e = hipSuccess;
+    auto M = [&](const float* in, float* outv) -> xrt_status {
+        info->operator_applies += 1;
+        return xrt_normal_apply(plan, lambda, in, outv, sa, stream);
+    };
+    // z = H^T (f * (H r)) + mu r
+    auto P = [&](const float* in, float* outv) -> xrt_status {
+        info->learned_accepted += 1;
+        xrt_status t = xrt_plan_forward(plan, in, sa, stream);
+        if (t != XRT_OK) return t;
+        hipError_t er = xrl::sino_filter(sa, pc->n_views, pc->n_bins, pc->filter, pc->taps, sb, s);
+        if (er != hipSuccess) return hip_fail("sino_filter", er);
+        t = xrt_plan_adjoint(plan, sb, outv, stream);
+        if (t != XRT_OK) return t;
+        if (pc->mu > 0.f) {
+            er = xrl::add_scaled(n, pc->mu, in, outv, s);
+            if (er != hipSuccess) return hip_fail("add_scaled", er);
+        }
+        return XRT_OK;
+    };
+    auto read_slots = [&]() -> hipError_t {
+        hipError_t er = hipMemcpyAsync(host, slots, S_N * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (er == hipSuccess) er = hipStreamSynchronize(s);
+        return er;
+    };
+    {
+        double bn = 0.0, rel = 1.0;
+        int hist_n = 0;
+        bool fresh = true, confirmed = false;
+        XS(xrl::fill_f32(x, n, 0.f, s), "fill");
+        XS(hipMemcpyAsync(r, b, n * sizeof(float), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+        XS(xrl::dots(n, b, b, nullptr, nullptr, nullptr, nullptr, dpart, slots, S_BB, s), "dots");
+        XS(read_slots(), "sync");
+        bn = sqrt(host[S_BB]);
+        if (bn == 0.0) {
+            info->converged = 1;
+            goto done;
+        }
+        while (true) {
+            if (rel <= tol) {
+                // confirm with the explicitly computed residual r = b - M x
+                XM(M(x, q));
+                XS(xrl::axpy2(n, slots, S_BB, S_BB, -1, b, q, r, nullptr, nullptr, nullptr, s), "axpy");
+                XS(xrl::dots(n, r, r, nullptr, nullptr, nullptr, nullptr, dpart, slots, T_RRN, s), "dots");
+                XS(read_slots(), "sync");
+                rel = sqrt(host[T_RRN]) / bn;
+                if (rel <= tol) {
+                    confirmed = true;
+                    break;
+                }
+                fresh = true;   // restart from the true residual
+            }
+            if (info->iterations >= maxit) break;
+            if (fresh) {
+                // p = z = P r, <r, z>
+                XM(P(r, z));
+                XS(xrl::dots(n, r, z, nullptr, nullptr, nullptr, nullptr, dpart, slots, T_RZ, s), "dots");
+                XS(hipMemcpyAsync(p, z, n * sizeof(float), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+                fresh = false;
+            }
+            XM(M(p, q));
+            XS(xrl::dots(n, p, q, nullptr, nullptr, nullptr, nullptr, dpart, slots, S_PQ, s), "dots");
+            // alpha = <r, z> / <p, M p>; x += alpha p; r -= alpha M p
+            XS(xrl::axpy2(n, slots, T_RZ, S_PQ, 1, x, p, x, r, q, r, s), "axpy");
+            XM(P(r, z));
+            // <r, z> (new) and <r, r>
+            XS(xrl::dots(n, r, z, r, r, nullptr, nullptr, dpart, slots, T_RZN, s), "dots");
+            // p = z + (<r, z>_new / <r, z>) p
+            XS(xrl::direction(n, slots, T_RZN, -1, T_RZ, z, p, p, s), "direction");
+            XS(xrl::copy_slot(slots, T_RZ, T_RZN, s), "copy");
+            XS(read_slots(), "sync");
+            rel = sqrt(host[T_RRN]) / bn;
+            info->iterations += 1;
+            if (history && hist_n < history_cap) history[hist_n++] = rel;
+        }
+        if (!confirmed) {
+            XM(M(x, q));
+            XS(xrl::axpy2(n, slots, S_BB, S_BB, -1, b, q, r, nullptr, nullptr, nullptr, s), "axpy");
+            XS(xrl::dots(n, r, r, nullptr, nullptr, nullptr, nullptr, dpart, slots, T_RRN, s), "dots");
+            XS(read_slots(), "sync");
+            rel = sqrt(host[T_RRN]) / bn;
+        }
+        info->rel_residual = rel;
+        info->converged = rel <= tol ? 1 : 0;
+    }
+done:
+    (void)hipStreamSynchronize(s);
+    (void)hipFreeAsync(ws, s);
+    (void)hipFreeAsync(slots, s);
+    (void)hipFreeAsync(dpart, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipHostFree(host);
+    return st;
+}
+
 }  // extern "C"

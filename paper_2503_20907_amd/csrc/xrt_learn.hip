@@ -674,6 +674,32 @@ __global__ void k_fill(float* p, int64_t n, float v)
     if (i < n) p[i] = v;
 }
 
+// out[v][j] = sum_k f[k] in[v][j + k - K/2], zero outside [0, nbins); one
+// thread per output
+__global__ __launch_bounds__(256) void k_sino_filter(const float* __restrict__ in, int64_t nviews, int nbins,
+                                                    const float* __restrict__ f, int K, float* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nviews * nbins) return;
+    const int64_t v = e / nbins;
+    const int j = (int)(e - v * nbins);
+    const float* row = in + v * nbins;
+    const int h = K / 2;
+    float acc = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const int jj = j + k - h;
+        if (jj >= 0 && jj < nbins) acc = fmaf(f[k], row[jj], acc);
+    }
+    out[e] = acc;
+}
+
+// z += mu * r
+__global__ void k_add_scaled(int64_t n, float mu, const float* __restrict__ r, float* __restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = fmaf(mu, r[i], z[i]);
+}
+
 // ------------------------------------------------------------- solver kernels
 __global__ void k_reg(const float* c, float* out, int nx, int ny, float lam, int accumulate)
 {
@@ -1003,6 +1029,21 @@ hipError_t pack_weights(const float* p, int taps, int cout, int cin, uint16_t* w
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t sino_filter(const float* in, int64_t nviews, int nbins, const float* f, int K, float* out, hipStream_t s)
+{
+    const int64_t n = nviews * nbins;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sino_filter, dim3(nblk(n)), dim3(256), 0, s, in, nviews, nbins, f, K, out);
+    return hipGetLastError();
+}
+
+hipError_t add_scaled(int64_t n, float mu, const float* r, float* z, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_scaled, dim3(nblk(n)), dim3(256), 0, s, n, mu, r, z);
     return hipGetLastError();
 }
 

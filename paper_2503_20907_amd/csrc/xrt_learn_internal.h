@@ -106,6 +106,10 @@ hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float l
 hipError_t pack_weights(const float* p, int taps, int cout, int cin, uint16_t* wf, uint16_t* wb,
                         hipStream_t s);
 hipError_t fill_f32(float* p, int64_t n, float v, hipStream_t s);
+// out[v][j] = sum_k f[k] in[v][j + k - K/2] over each view's nbins samples (zero outside)
+hipError_t sino_filter(const float* in, int64_t nviews, int nbins, const float* f, int K, float* out, hipStream_t s);
+// z += mu r
+hipError_t add_scaled(int64_t n, float mu, const float* r, float* z, hipStream_t s);
 // wb[taps-1-tap][i][o] = w[tap][o][i]
 hipError_t flip_weights(const uint16_t* w, int taps, int cout, int cin, uint16_t* wb, hipStream_t s);
 

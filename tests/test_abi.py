@@ -178,3 +178,19 @@ def test_batch_entry_points_reject_bad_arguments():
     assert lib.xrt_batch_autotune(None, 1, None, None) == L.XRT_EINVAL
     assert lib.xrt_batch_info(None, None, None, None) == L.XRT_EINVAL
     assert lib.xrt_batch_buffers(None, 0, None, None, None) == L.XRT_EINVAL
+
+
+def test_sino_filter_and_pcg_reject_bad_arguments():
+    lib = L.load()
+    F = 0x1000  # never dereferenced: validation fails first
+    assert lib.xrt_sino_filter(None, 2, 8, F, 3, F, None) == L.XRT_EINVAL
+    assert lib.xrt_sino_filter(F, 2, 8, None, 3, F, None) == L.XRT_EINVAL
+    assert lib.xrt_sino_filter(F, 2, 8, F, 3, None, None) == L.XRT_EINVAL
+    assert lib.xrt_sino_filter(F, -1, 8, F, 3, F, None) == L.XRT_EINVAL
+    assert lib.xrt_sino_filter(F, 2, 0, F, 3, F, None) == L.XRT_EINVAL
+    for taps in (0, 2, 65, -3):
+        assert lib.xrt_sino_filter(F, 2, 8, F, taps, F, None) == L.XRT_EINVAL, taps
+    info = L.XrtSolveInfo()
+    pc = L.XrtSinoPrecond(2, 8, 3, F, 0.0, 0)
+    assert lib.xrt_solve_sino_pcg(None, ctypes.c_float(1.0), F, F, ctypes.c_float(1e-3), 10, ctypes.byref(pc),
+                                  ctypes.byref(info), None, 0, None) == L.XRT_EPLAN

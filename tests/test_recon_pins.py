@@ -215,3 +215,47 @@ def test_residual_loss_gradient_matches_central_differences():
     z = R.precondition(flat, r, levels, base, gain=0.3)
     ref = np.mean([np.sum((R.normal_apply(n, z[b], lc, lam) - r[b]) ** 2) / np.sum(r[b] ** 2) for b in range(2)])
     assert abs(loss - ref) < 1e-12 * ref
+
+
+# ------------------------------------------------- sinogram filter preconditioner
+def test_sino_filter_matches_scipy_correlate1d():
+    from scipy.ndimage import correlate1d
+    rng = _rng(31)
+    for n_views, n_bins, K in ((3, 17, 5), (2, 4, 9), (4, 40, 1), (1, 3, 63)):
+        s = rng.normal(size=(n_views, n_bins))
+        f = rng.normal(size=K)
+        ref = correlate1d(s, f, axis=1, mode="constant", cval=0.0)
+        got = R.sino_filter(s.ravel(), n_views, n_bins, f).reshape(n_views, n_bins)
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_pcg_with_identity_is_cg_and_with_the_inverse_takes_one_step():
+    n, N, lam = 1, 6, 0.05
+    lc, H = _tiny_problem(n, N)
+    b = _rng(32).normal(size=(N, N))
+    A = lambda v: R.normal_apply(n, v, lc, lam)
+    x1, it1, h1 = R.cg(A, b, tol=1e-10, maxit=200)
+    x2, it2, h2 = R.pcg(A, lambda r: r, b, tol=1e-10, maxit=200)
+    assert it1 == it2 and np.allclose(h1, h2, rtol=1e-9) and np.allclose(x1, x2, rtol=1e-9, atol=1e-12)
+    Lt = np.stack([R.reg_apply(np.eye(N * N)[k].reshape(N, N), 1.0).ravel() for k in range(N * N)], axis=1)
+    Minv = np.linalg.inv(H.T @ H + lam * Lt)
+    x3, it3, _ = R.pcg(A, lambda r: (Minv @ r.ravel()).reshape(N, N), b, tol=1e-10, maxit=200)
+    assert it3 == 1 and np.allclose(x3.ravel(), Minv @ b.ravel(), rtol=1e-9, atol=1e-12)
+
+
+def test_sino_preconditioner_is_the_filtered_normal_product():
+    # P r = H^T F H r + mu r with F the dense filter matrix of each view
+    n, N = 1, 6
+    lc, H = _tiny_problem(n, N)
+    m = H.shape[0]
+    n_views, n_bins = 1, m
+    f = np.array([-1.0, 2.0, -1.0])
+    F = np.stack([R.sino_filter(np.eye(m)[k], n_views, n_bins, f) for k in range(m)], axis=1)
+    r = _rng(33).normal(size=(N, N))
+    got = R.sino_precondition(n, r, lc, f, 0.25, n_views, n_bins)
+    ref = (H.T @ (F @ (H @ r.ravel()))).reshape(N, N) + 0.25 * r
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-10)
+    # a positive second difference filter gives a positive semi-definite P
+    Pd = np.stack([R.sino_precondition(n, np.eye(N * N)[k].reshape(N, N), lc, f, 0.0, n_views, n_bins).ravel()
+                   for k in range(N * N)], axis=1)
+    assert np.allclose(Pd, Pd.T, atol=1e-10) and np.linalg.eigvalsh(0.5 * (Pd + Pd.T)).min() > -1e-10
