@@ -119,7 +119,11 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
                            xrt_plan** out);
 
 /* Forward / adjoint with a plan: the hot path.  No synchronisation, no
- * allocation. */
+ * allocation.  Repeated calls with one plan give bitwise-identical results.
+ * Two plans built from the same lines can order the lines of a bucket
+ * differently (the plan's counting sort scatters with atomics).  The forward
+ * does not depend on that order; the adjoint's fixed-point rounding does, by
+ * about one FP32 rounding (1e-7 relative). */
 xrt_status xrt_plan_forward(const xrt_plan* p, const float* coeffs, float* sino, void* stream);
 xrt_status xrt_plan_adjoint(const xrt_plan* p, const float* sino, float* coeffs_out,
                             void* stream);

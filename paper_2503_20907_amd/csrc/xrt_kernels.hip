@@ -867,6 +867,10 @@ struct AdjArgs {
 // halos
 constexpr int kAccWords = kTileJ * (kTileI + 2 * kHalo + 1);
 constexpr int kPix = kTileI * kTileJ / kBlock;
+// every thread flushes kPix whole pixels, and the candidate scan takes the
+// slope bins two per thread
+static_assert(kTileI * kTileJ % kBlock == 0, "a tile must hold a whole number of pixels per thread");
+static_assert(kSlopeBins == 2 * kBlock, "the candidate scan assumes two slope bins per thread");
 
 // The LDS accumulators are int32 fixed point: float atomic adds to LDS are an
 // order of magnitude slower than integer ones on gfx950.  Lines are taken in
