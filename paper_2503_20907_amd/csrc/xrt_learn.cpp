@@ -80,6 +80,58 @@ xrt_status hip_fail(const char* what, hipError_t e)
         if (e_ != hipSuccess) return hip_fail(what, e_);       \
     } while (0)
 
+// The temporary buffers of one entry point, released on every return path:
+// device buffers with hipFreeAsync on the entry point's stream, the pinned
+// host buffer once that stream has drained (on an error path a copy into it
+// may still be queued).
+class Scratch {
+public:
+    explicit Scratch(hipStream_t s) : s_(s) {}
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+    template <typename T>
+    hipError_t device(T** out, size_t bytes)
+    {
+        *out = nullptr;
+        if (n_ == kMax) return hipErrorInvalidValue;
+        void* p = nullptr;
+        const hipError_t e = hipMallocAsync(&p, bytes, s_);
+        if (e == hipSuccess) {
+            dev_[n_++] = p;
+            *out = (T*)p;
+        }
+        return e;
+    }
+    template <typename T>
+    hipError_t host(T** out, size_t bytes)
+    {
+        *out = nullptr;
+        if (host_) return hipErrorInvalidValue;
+        void* p = nullptr;
+        const hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        if (e == hipSuccess) {
+            host_ = p;
+            *out = (T*)p;
+        }
+        return e;
+    }
+    ~Scratch()
+    {
+        for (int i = n_ - 1; i >= 0; --i) (void)hipFreeAsync(dev_[i], s_);
+        if (host_) {
+            (void)hipStreamSynchronize(s_);
+            (void)hipHostFree(host_);
+        }
+    }
+
+private:
+    static constexpr int kMax = 4;
+    hipStream_t s_;
+    void* dev_[kMax] = {};
+    int n_ = 0;
+    void* host_ = nullptr;
+};
+
 bool net_ok(const xrt_unet* n) { return n && n->magic == kNetMagic; }
 
 int enc_a(const xrt_unet* n, int l) { (void)n; return 2 * l; }
@@ -640,8 +692,9 @@ xrt_status xrt_conv3x3_grad_input(const uint16_t* gy, const uint16_t* w, int32_t
     if (st != XRT_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const int64_t nw = (int64_t)9 * cout * cin;
+    Scratch tmp(s);
     uint16_t* wflip = nullptr;
-    XL_CHECK(hipMallocAsync((void**)&wflip, nw * sizeof(uint16_t), s), "hipMallocAsync");
+    XL_CHECK(tmp.device(&wflip, nw * sizeof(uint16_t)), "hipMallocAsync");
     XL_CHECK(xrl::flip_weights(w, 9, cout, cin, wflip, s), "flip_weights");
     xrl::ConvArgs a;
     a.x = CView{gy, cout};
@@ -657,11 +710,8 @@ xrt_status xrt_conv3x3_grad_input(const uint16_t* gy, const uint16_t* w, int32_t
     a.relu = 0;
     const int64_t wn = xrl::conv3x3_ws_floats(B, H, W, cout, cin);
     float* ws = nullptr;
-    if (wn > 0) XL_CHECK(hipMallocAsync((void**)&ws, wn * sizeof(float), s), "hipMallocAsync");
-    hipError_t e = xrl::conv3x3(a, true, ws, wn, s);
-    if (ws) (void)hipFreeAsync(ws, s);
-    (void)hipFreeAsync(wflip, s);
-    XL_CHECK(e, "conv3x3");
+    if (wn > 0) XL_CHECK(tmp.device(&ws, wn * sizeof(float)), "hipMallocAsync");
+    XL_CHECK(xrl::conv3x3(a, true, ws, wn, s), "conv3x3");
     return XRT_OK;
 }
 
@@ -681,11 +731,11 @@ xrt_status xrt_conv3x3_grad_weight(const uint16_t* x, const uint16_t* gy, int32_
     a.cout = cout;
     a.rows = xrl::wgrad_rows(B, H, W, cin, cout);
     const int64_t nreg = xrl::wgrad_regions(B, H, W, a.rows);
-    XL_CHECK(hipMallocAsync((void**)&a.part, (size_t)nreg * 9 * cin * cout * sizeof(float), s), "hipMallocAsync");
+    Scratch tmp(s);
+    XL_CHECK(tmp.device(&a.part, (size_t)nreg * 9 * cin * cout * sizeof(float)), "hipMallocAsync");
     int nr = 0;
     XL_CHECK(xrl::conv3x3_wgrad(a, &nr, s), "conv3x3_wgrad");
     XL_CHECK(xrl::reduce_parts(a.part, nr, (int64_t)9 * cin * cout, gw, s), "reduce");
-    (void)hipFreeAsync(a.part, s);
     return XRT_OK;
 }
 
@@ -732,14 +782,13 @@ xrt_status xrt_solve_ex(const xrt_plan* plan, float lambda, const float* b, floa
 
     // workspace: r, r_new, x_new, p_new, q, z, p (CG), then 2*win ring vectors; one sinogram; scalars
     const int nvec = 7 + 2 * win;
+    Scratch tmp(s);
     float* ws = nullptr;
     double *slots = nullptr, *dpart = nullptr, *host = nullptr;
-    XL_CHECK(hipMallocAsync((void**)&ws, ((size_t)nvec * n + (size_t)(m > 0 ? m : 1)) * sizeof(float), s),
-             "hipMallocAsync");
-    XL_CHECK(hipMallocAsync((void**)&slots, S_N * sizeof(double), s), "hipMallocAsync");
-    XL_CHECK(hipMallocAsync((void**)&dpart, (size_t)xrl::kMaxVecs * xrl::dots_parts() * sizeof(double), s),
-             "hipMallocAsync");
-    XL_CHECK(hipHostMalloc((void**)&host, S_N * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    XL_CHECK(tmp.device(&ws, ((size_t)nvec * n + (size_t)(m > 0 ? m : 1)) * sizeof(float)), "hipMallocAsync");
+    XL_CHECK(tmp.device(&slots, S_N * sizeof(double)), "hipMallocAsync");
+    XL_CHECK(tmp.device(&dpart, (size_t)xrl::kMaxVecs * xrl::dots_parts() * sizeof(double)), "hipMallocAsync");
+    XL_CHECK(tmp.host(&host, S_N * sizeof(double)), "hipHostMalloc");
     float *r = ws, *rn = ws + n, *xn = ws + 2 * n, *pn = ws + 3 * n, *q = ws + 4 * n, *z = ws + 5 * n,
           *p = ws + 6 * n, *sino = ws + (size_t)nvec * n;
     float* P[xrl::kMaxVecs];
@@ -887,11 +936,6 @@ xrt_status xrt_solve_ex(const xrt_plan* plan, float lambda, const float* b, floa
     }
 done:
     (void)hipStreamSynchronize(s);
-    (void)hipFreeAsync(ws, s);
-    (void)hipFreeAsync(slots, s);
-    (void)hipFreeAsync(dpart, s);
-    (void)hipStreamSynchronize(s);
-    (void)hipHostFree(host);
     return st;
 }
 
@@ -924,13 +968,13 @@ xrt_status xrt_solve_sino_pcg(const xrt_plan* plan, float lambda, const float* b
     const int64_t ms = m > 0 ? m : 1;
 
     // workspace: r, z, p, q; two sinograms; scalars
+    Scratch tmp(s);
     float* ws = nullptr;
     double *slots = nullptr, *dpart = nullptr, *host = nullptr;
-    XL_CHECK(hipMallocAsync((void**)&ws, ((size_t)4 * n + 2 * (size_t)ms) * sizeof(float), s), "hipMallocAsync");
-    XL_CHECK(hipMallocAsync((void**)&slots, S_N * sizeof(double), s), "hipMallocAsync");
-    XL_CHECK(hipMallocAsync((void**)&dpart, (size_t)xrl::kMaxVecs * xrl::dots_parts() * sizeof(double), s),
-             "hipMallocAsync");
-    XL_CHECK(hipHostMalloc((void**)&host, S_N * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    XL_CHECK(tmp.device(&ws, ((size_t)4 * n + 2 * (size_t)ms) * sizeof(float)), "hipMallocAsync");
+    XL_CHECK(tmp.device(&slots, S_N * sizeof(double)), "hipMallocAsync");
+    XL_CHECK(tmp.device(&dpart, (size_t)xrl::kMaxVecs * xrl::dots_parts() * sizeof(double)), "hipMallocAsync");
+    XL_CHECK(tmp.host(&host, S_N * sizeof(double)), "hipHostMalloc");
     float *r = ws, *z = ws + n, *p = ws + 2 * n, *q = ws + 3 * n, *sa = ws + 4 * n, *sb = sa + ms;
 
     hipError_t e = hipSuccess;
@@ -1020,11 +1064,6 @@ xrt_status xrt_solve_sino_pcg(const xrt_plan* plan, float lambda, const float* b
     }
 done:
     (void)hipStreamSynchronize(s);
-    (void)hipFreeAsync(ws, s);
-    (void)hipFreeAsync(slots, s);
-    (void)hipFreeAsync(dpart, s);
-    (void)hipStreamSynchronize(s);
-    (void)hipHostFree(host);
     return st;
 }
 
