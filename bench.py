@@ -8,8 +8,9 @@ Inputs are device-resident when timing starts.  Prints one JSON line.
 
 The line also carries "recon": time to relative residual 1e-3 of the
 Tikhonov normal equations (lambda 1e-2) on a 512 x 512 cubic grid with
-180 x 768 parallel-beam Poisson-noisy data, plain CG against flexible CG with
-the trained U-Net preconditioner (training time reported separately).
+180 x 768 parallel-beam Poisson-noisy data: plain CG, flexible CG with the
+trained U-Net preconditioner (training time reported separately), and CG
+preconditioned by the second-difference sinogram filter.
 
 It also carries "batch": 64 uneven problems in persistent launches (one for
 the forward, two for the adjoint; with graph replay and the autotuner) against
@@ -65,7 +66,6 @@ def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
     (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or None if
     the kernel source changed since the counters were taken."""
-    import hashlib
     import re
     srcs = [os.path.join(ROOT, "paper_2503_20907_amd", "csrc", f) for f in KERNEL_SOURCES]
     summ = os.path.join(ROOT, "profiles", "hbm_traffic_2048_cubic_fan_random.md")
