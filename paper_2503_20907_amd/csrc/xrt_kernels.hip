@@ -874,11 +874,12 @@ static_assert(kSlopeBins == 2 * kBlock, "the candidate scan assumes two slope bi
 
 // The LDS accumulators are int32 fixed point: float atomic adds to LDS are an
 // order of magnitude slower than integer ones on gfx950.  Lines are taken in
-// chunks of 2 kBlock (two per thread); a chunk scales the tap contributions by
-// 2^e with e = 21 - exponent(max |s| over the chunk), so each of them
-// (|s w| <= |s|, since |w| <= 1) is below 2^21 in magnitude and the at most
-// 2 kBlock contributions a chunk makes to one accumulator word (one per line)
-// stay below 2^30.  The knot contributions r^n E s are bounded by G(0) |s|
+// chunks of 2 kBlock (two per thread; 8 kBlock for the box spline); a chunk
+// scales the tap contributions by 2^e with e = 21 - exponent(max |s| over the
+// chunk) (19 - for 8 kBlock lines), so each of them (|s w| <= |s|, since
+// |w| <= 1) is below 2^21 (2^19) in magnitude and the at most 2 kBlock
+// (8 kBlock) contributions a chunk makes to one accumulator word (one per
+// line) stay below 2^30.  The knot contributions r^n E s are bounded by G(0) |s|
 // (G(0) = 1/2, 1/6, 1/16, 0.0246 for n = 0..3) and get 2^kKnotShift more
 // resolution under the same bound.  After each chunk the integers are
 // converted back (scaled exactly by powers of two) into per-thread FP32
@@ -887,6 +888,16 @@ static_assert(kSlopeBins == 2 * kBlock, "the candidate scan assumes two slope bi
 // the order of the atomics.
 template <int N>
 __device__ constexpr int knot_shift() { return N == 0 ? 1 : N == 1 ? 2 : N == 2 ? 4 : 5; }
+// Lines per thread and chunk, and the scale exponent's bound that keeps a
+// chunk's adj_lpt kBlock contributions to one word below 2^30.  The box
+// spline's rows are cheap, so the per-chunk work (candidate search, maximum,
+// flush) weighs more: 8 lines per thread took its 2048^2 adjoint from 12.6 to
+// 11.6 ms; the cubic spline is fastest at 2 (24.9 ms; 25.1 at 4, 25.5 at 8).
+template <int N>
+__device__ constexpr int adj_lpt() { return N == kBox3 ? 8 : 2; }
+template <int N>
+__device__ constexpr int adj_scale_bits() { return adj_lpt<N>() == 2 ? 21 : adj_lpt<N>() == 4 ? 20 : 19; }
+constexpr int kAdjLptMax = 8;
 
 // Round-to-nearest integer of a float below 2^22 in magnitude: adding
 // 1.5 * 2^23 leaves exactly the rounded value in the mantissa.
@@ -1162,7 +1173,7 @@ struct AdjShared {
     uint32_t start[kSlopeBins];
     uint32_t pre[kSlopeBins + 1];
     uint32_t scan[kBlock];
-    uint32_t run[16];   // slope bins of the first and last item of each run of 64 items of a chunk
+    uint32_t run[8 * kAdjLptMax];  // slope bins of the first and last item of each run of 64 items of a chunk
     float red[4];
 };
 
@@ -1258,12 +1269,15 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
         __syncthreads();
         const uint32_t total = s_pre[kSlopeBins];
 
-        for (uint32_t base = (uint32_t)kpart * 2u * kBlock; base < total; base += (uint32_t)A.split * 2u * kBlock) {
+        constexpr int kAdjLpt = adj_lpt<N>();
+        static_assert(kAdjLpt <= kAdjLptMax, "run table too small");
+        constexpr uint32_t kChunk = (uint32_t)kAdjLpt * kBlock;
+        for (uint32_t base = (uint32_t)kpart * kChunk; base < total; base += (uint32_t)A.split * kChunk) {
             // item -> slope bin b with s_pre[b] <= item < s_pre[b+1].  Each
             // wave takes runs of 64 consecutive items; 16 threads first find
             // the bins of every run's first and last item, so that a lane
             // then searches only the few bins its run spans.
-            if (tid < 16) {
+            if (tid < 8 * kAdjLpt) {
                 const uint32_t first = base + (uint32_t)((tid >> 3) * kBlock + ((tid >> 1) & 3) * 64);
                 uint32_t it = first;
                 if (tid & 1) it = min(first + 63u, total - 1u);
@@ -1278,10 +1292,13 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                 sh.run[tid] = (uint32_t)lo;
             }
             __syncthreads();
-            uint32_t kk[2] = {0, 0};
-            float svv[2] = {0.f, 0.f};
+            uint32_t kk[kAdjLpt];
+            float svv[kAdjLpt];
+            float amax = 0.f;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < kAdjLpt; ++u) {
+                kk[u] = 0;
+                svv[u] = 0.f;
                 const uint32_t item = base + (uint32_t)(u * kBlock + tid);
                 if (item < total) {
                     const int r = (u << 3) | ((tid >> 6) << 1);
@@ -1294,16 +1311,17 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                     kk[u] = s_start[lo] + (item - s_pre[lo]);
                     svv[u] = A.sw[kk[u]];
                 }
+                amax = fmaxf(amax, fabsf(svv[u]));
             }
-            const float mx = block_max(fmaxf(fabsf(svv[0]), fabsf(svv[1])), s_red);
+            const float mx = block_max(amax, s_red);
             if (!(mx > 0.f)) continue;  // uniform: nothing to add in this chunk
             int em;
             (void)frexpf(mx, &em);
-            // |s| 2^e < 2^21 (every row weight is at most 1)
-            const int e = 21 - em;
+            // |s| 2^e < 2^adj_scale_bits (every row weight is at most 1)
+            const int e = adj_scale_bits<N>() - em;
             const double kscale = ldexp(1.0, -e - knot_shift<N>());
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < kAdjLpt; ++u) {
                 if constexpr (N == kBox3)
                     adj_line_box(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg,
                                  s_a);
