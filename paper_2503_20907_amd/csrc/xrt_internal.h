@@ -14,8 +14,12 @@ constexpr int kPad = 8;
 // Slope bins of the plan (the slope kappa of a line lies in [-1, 1]).
 constexpr int kSlopeBins = 512;
 // Intervals per unit of the knot-transition table.
-constexpr int kTabPerUnit = 64;
-// Largest table: degree 3, half-support 2 -> 128 intervals + 1 zero interval.
+// 16 (cubic Hermite error at most 2.7e-8 for degree 3, 3.9e-8 for degree 2,
+// exact for degrees 0 and 1) rather than 64 (1.6e-10): lanes of a wave then
+// read the same entry more often, with fewer LDS bank conflicts (2048^2 cubic
+// adjoint 25.2 -> 24.3 ms, forward 13.8 -> 13.7 ms).
+constexpr int kTabPerUnit = 16;
+// Largest table: degree 3, half-support 2 -> 32 intervals + 1 zero interval.
 constexpr int kTabMax = kTabPerUnit * 2 + 1;
 // Adjoint tile (pixels): kTileI columns (x1) by kTileJ rows (x2) for the
 // vertical lines, and the transposed tile for the horizontal ones (kTileI

@@ -22,7 +22,7 @@
 // (plus the r^2 beta'' term), and D_K = sum_l delta_l c_{K-l} the (n+1)-th
 // backward difference of the row at knot K.  At most n+1 knots K lie within
 // (n+1) r / 2 of X, so a row costs n+1 taps plus n+1 knot slots whatever r
-// is.  E is a cubic-per-interval table (64 intervals per unit) built in FP64
+// is.  E is a cubic-per-interval table (16 intervals per unit) built in FP64
 // on the host and copied to LDS; the adjoint reads part of its entries from
 // the global copy instead (adj_mem_slots).  Line geometry (crossings, floors)
 // is FP64; the row arithmetic is FP32 in local coordinates t in [0, 1).
@@ -315,11 +315,11 @@ __global__ void __launch_bounds__(kBlock) k_layout_h(const float* __restrict__ c
 }
 
 // ---------------------------------------------------------------- row math
-// Constants of one line: 64/r (table units), r^n, the beta'' weight rho, and
+// Constants of one line: kTabPerUnit/r (table units), r^n, the beta'' weight rho, and
 // the number of knot slots S = ceil((n+1) r) (at most n+1) that can be
 // non-zero in a row: only knots within (n+1) r / 2 of the crossing matter.
 struct LineConst {
-    float inv64, rn, rho;
+    float inv_tab, rn, rho;
     int slots;
 };
 
@@ -328,7 +328,7 @@ __device__ inline LineConst line_const(double kap)
 {
     LineConst k;
     const float r = (float)fabs(kap);
-    k.inv64 = (float)kTabPerUnit / fmaxf(r, 1e-30f);
+    k.inv_tab = (float)kTabPerUnit / fmaxf(r, 1e-30f);
     float rn = 1.f;
 #pragma unroll
     for (int e = 0; e < N; ++e) rn *= r;
@@ -351,7 +351,7 @@ __device__ inline int wave_slots(int mine)
     return S;
 }
 
-// Knot-transition table at z64 = 64 z: g(|z|) with the parity of E
+// Knot-transition table at zt = kTabPerUnit z: g(|z|) with the parity of E
 // (E is even for odd n; for even n it changes sign at 0).
 // Table entries are read as a uniform base plus a 32-bit byte offset.  The
 // global copy is typed in the global address space: through a generic pointer
@@ -368,15 +368,15 @@ __device__ inline f4v tab_at(const float4* tab, uint32_t byte)
 __device__ inline f4v tab_at(const GTab* tab, uint32_t byte) { return *(const GTab*)((const GByte*)tab + byte); }
 
 template <int N, typename T>
-__device__ inline float etab64(const T* __restrict__ tab, float z64)
+__device__ inline float etab(const T* __restrict__ tab, float zt)
 {
     constexpr int last = kTabPerUnit * (N + 1) / 2;  // index of the zero interval
-    const float a = fminf(fabsf(z64), (float)last);
+    const float a = fminf(fabsf(zt), (float)last);
     const int i = (int)a;
     const float tau = __builtin_amdgcn_fractf(a);
     const f4v cf = tab_at(tab, (uint32_t)i << 4);
     float g = fmaf(tau, fmaf(tau, fmaf(tau, cf.w, cf.z), cf.y), cf.x);
-    if constexpr (N % 2 == 0) g = z64 >= 0.f ? -g : g;
+    if constexpr (N % 2 == 0) g = zt >= 0.f ? -g : g;
     return g;
 }
 
@@ -412,19 +412,19 @@ __device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>
     if constexpr (S % 2 == 1) {
         const bool up = t >= 0.5f;
         o = (up ? 1 : 0) - (S - 1) / 2;
-        oz = up ? (float)(1 - (S - 1) / 2) * k.inv64 : (float)(-((S - 1) / 2)) * k.inv64;
+        oz = up ? (float)(1 - (S - 1) / 2) * k.inv_tab : (float)(-((S - 1) / 2)) * k.inv_tab;
     } else {
         o = 1 - S / 2;
-        oz = (float)o * k.inv64;
+        oz = (float)o * k.inv_tab;
     }
     R.K0 = R.J + o;
     // z_s = (q - K0 - s) / r, in table units
-    const float a0 = fmaf(t, k.inv64, -oz);
-    R.g[0] = G > 0 ? etab64<N>(tab.mem, a0) : etab64<N>(tab.lds, a0);
+    const float a0 = fmaf(t, k.inv_tab, -oz);
+    R.g[0] = G > 0 ? etab<N>(tab.mem, a0) : etab<N>(tab.lds, a0);
 #pragma unroll
     for (int sl = 1; sl < S; ++sl) {
-        const float z = fmaf(-(float)sl, k.inv64, a0);
-        R.g[sl] = sl < G ? etab64<N>(tab.mem, z) : etab64<N>(tab.lds, z);
+        const float z = fmaf(-(float)sl, k.inv_tab, a0);
+        R.g[sl] = sl < G ? etab<N>(tab.mem, z) : etab<N>(tab.lds, z);
     }
 }
 
