@@ -392,7 +392,8 @@ struct Row {
 // The two copies of the E table a row reads: knot slots below G take the
 // global copy (through the vector L1 cache), the others the LDS copy.  The
 // forward reads all of them from LDS (G = 0): its vector memory path is busy
-// with the coefficient loads.
+// with the coefficient loads (one or two of the cubic reads through the L1:
+// 2048^2 forward 13.8 -> 19.0 or 23.7 ms).
 struct TabRef {
     const float4* lds;
     const GTab* mem;
