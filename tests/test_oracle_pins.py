@@ -357,6 +357,62 @@ def test_line_invariances(orc):
     np.testing.assert_allclose(shifted, orc.forward(n, c, moved), atol=1e-12)
 
 
+def _endpoint_reference(ep):
+    """Direction and offset of the line through p and q, by formulas other
+    than the oracle's: theta = atan2(dy, dx), and y = <p, theta_perp> written
+    as the 2-D cross product p x q / |q - p| (eq. (1): theta_perp =
+    (sin, -cos), so <p, theta_perp> = (px dy - py dx)/|q - p| = p x q / |q - p|)."""
+    e = np.asarray(ep, dtype=np.float64).reshape(-1, 4)
+    px, py, qx, qy = e[:, 0], e[:, 1], e[:, 2], e[:, 3]
+    th = np.arctan2(qy - py, qx - px)
+    y = (px * qy - py * qx) / np.hypot(qx - px, qy - py)
+    return th, y
+
+
+@pytest.mark.parametrize("geometry", ["random", "fan"])
+def test_endpoint_lines_match_theta_y(orc, geometry):
+    """P11 / eq. (1): the line through two points equals the (theta, y) line
+    with theta along q - p and y = <p, theta_perp>; reversing the points gives
+    the same line as (theta + pi, -y).  Checked against atan2 and the cross
+    product, and through the forward of both line forms."""
+    import xrt_workloads as W
+    rng = np.random.default_rng(71)
+    N, n = 24, 3
+    if geometry == "random":
+        m = 400
+        th = rng.uniform(-math.pi, 2 * math.pi, size=m)
+        y = rng.uniform(-14, 14, size=m)
+        a = rng.uniform(-40, 40, size=m)
+        b = a + rng.choice([-1, 1], size=m) * rng.uniform(0.5, 60, size=m)
+        tv = np.stack([np.cos(th), np.sin(th)], 1)
+        nv = np.stack([np.sin(th), -np.cos(th)], 1)
+        p = y[:, None] * nv + a[:, None] * tv
+        q = y[:, None] * nv + b[:, None] * tv
+        ep = np.concatenate([p, q], 1).astype(np.float32)
+    else:
+        ep = W.fan_beam(30, 40, 60.0, N, n)["endpoints"]
+    c = rng.normal(size=(N, N))
+    ref_th, ref_y = _endpoint_reference(ep)
+    cs, sn, yy = orc.lines_from_endpoints(ep)
+    np.testing.assert_allclose(cs, np.cos(ref_th), atol=1e-12)
+    np.testing.assert_allclose(sn, np.sin(ref_th), atol=1e-12)
+    np.testing.assert_allclose(yy, ref_y, atol=1e-9)
+    # the reversed pair is the same line as (theta + pi, -y)
+    cr, sr, yr = orc.lines_from_endpoints(ep[:, [2, 3, 0, 1]])
+    np.testing.assert_allclose(cr, -cs, atol=1e-12)
+    np.testing.assert_allclose(sr, -sn, atol=1e-12)
+    np.testing.assert_allclose(yr, -yy, atol=1e-9)
+    # forward of the endpoint form against the theta_y form of the same lines
+    # (theta and y rounded to float32 on their way in: ~1e-7 relative)
+    f_ep = orc.forward(n, c, (cs, sn, yy))
+    f_ty = orc.forward(n, c, orc.lines_from_theta_y(ref_th.astype(np.float32), ref_y.astype(np.float32)))
+    scale = np.abs(f_ty).max()
+    assert scale > 1.0
+    np.testing.assert_allclose(f_ep, f_ty, atol=2e-4 * scale)
+    # most lines cross the grid: the comparison is not between zeros
+    assert np.count_nonzero(np.abs(f_ty) > 1e-3 * scale) > 0.5 * len(f_ty)
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 3])
 def test_band_equals_dense(orc, n):
     """P12: the band enumeration drops no nonzero term: bit-for-bit equal to
