@@ -288,9 +288,9 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     uint32_t* count = al.get<uint32_t>(p->key_space);
     const int64_t scan_words = scan_tmp_words(p->key_space);
     uint32_t* scan_tmp = al.get<uint32_t>(scan_words);
-    uint32_t* cursor = al.get<uint32_t>(p->key_space + 1);
+    uint32_t* sort_tmp = al.get<uint32_t>(radix_tmp_words(m, p->key_space - 1));
     auto free_tmp = [&]() {
-        void* t[] = {key, xc_in, kap_in, count, scan_tmp, cursor};
+        void* t[] = {key, xc_in, kap_in, count, scan_tmp, sort_tmp};
         for (void* q : t)
             if (q) (void)hipFreeAsync(q, s);
     };
@@ -337,19 +337,17 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     ca.hdr = p->hdr;
     XRT_TRY(launch_canon(ca, s), "canonicalize");
     XRT_TRY(launch_scan(count, p->off, p->key_space, scan_tmp, s), "scan");
-    XRT_TRY(hipMemcpyAsync(cursor, p->off, sizeof(uint32_t) * p->key_space,
-                           hipMemcpyDeviceToDevice, s),
-            "copy");
-    ScatterArgs sa;
+    SortArgs sa;
     sa.m = m;
+    sa.max_key = (uint32_t)(p->key_space - 1);
     sa.key = key;
+    sa.tmp = sort_tmp;
     sa.xc_in = xc_in;
     sa.kap_in = kap_in;
-    sa.cursor = cursor;
     sa.xc = p->xc;
     sa.kap = p->kap;
     sa.idx = p->idx;
-    XRT_TRY(launch_scatter(sa, s), "scatter");
+    XRT_TRY(launch_radix_sort(sa, s), "sort");
     XRT_TRY(launch_header(p->hdr, p->off, per_v, per_v + per_h, s), "header");
     PlanHeader h;
     memset(&h, 0, sizeof(h));

@@ -151,8 +151,12 @@ hipError_t enqueue_adjoint(xrt_batch* b, hipStream_t s)
     e = xrt::launch_batch_adjoint(b->probs, b->items_a, b->nitems_a, b->counters + 1,
                                   b->cus * b->cfg.adj_blocks_per_cu, 0, s);
     if (e != hipSuccess) return e;
-    return xrt::launch_batch_adjoint(b->probs, b->items_ah, b->nitems_ah, b->counters + 2,
-                                     b->cus * b->cfg.adj_blocks_per_cu, 1, s);
+    e = xrt::launch_batch_adjoint(b->probs, b->items_ah, b->nitems_ah, b->counters + 2,
+                                  b->cus * b->cfg.adj_blocks_per_cu, 1, s);
+    if (e != hipSuccess) return e;
+    int64_t max_m = 0;
+    for (xrt_plan* p : b->plans) max_m = std::max<int64_t>(max_m, p->m);
+    return xrt::launch_batch_nonfinite(b->probs, b->count, max_m, s);
 }
 
 void drop_graph(xrt_batch* b)

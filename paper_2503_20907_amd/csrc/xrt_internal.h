@@ -79,26 +79,56 @@ struct CanonArgs {
     xrt::PlanHeader* hdr;
 };
 
-struct ScatterArgs {
+// Stable sort of the plan's lines by key (LSD radix sort, 8 bits per pass).
+struct SortArgs {
     int64_t m;
-    const uint32_t* key;
-    const double* xc_in;
+    uint32_t max_key;      // largest key value (sets the number of passes)
+    uint32_t* key;         // [m] keys; overwritten (used as a ping-pong buffer)
+    uint32_t* tmp;         // radix_tmp_words(m, max_key) words
+    const double* xc_in;   // [m] line records in input order
     const double* kap_in;
-    uint32_t* cursor;
-    double* xc;
+    double* xc;            // [m] line records in sorted order
     double* kap;
-    int32_t* idx;
+    int32_t* idx;          // [m] input position of each sorted line
+};
+
+struct RadixArgs {
+    const uint32_t* key_in;
+    const uint32_t* val_in;  // null: the element's own index
+    uint32_t* key_out;
+    uint32_t* val_out;
+    int64_t m;
+    int shift;
+    const uint32_t* hoff;    // [256][nblk] first output position of every (digit, workgroup)
+    int nblk;
+};
+
+// Lines with a non-finite sinogram value (k_adj_nonfinite).
+struct NonFiniteArgs {
+    int64_t m;
+    const PlanHeader* hdr;
+    const double* xc;
+    const double* kap;
+    const float* sw;   // [m] sinogram in sorted order (scaled)
+    int nx, ny;
+    int degree;        // B-spline degree (geometry degree for the box spline)
+    int box;           // 1: the box spline's support
+    float* out;
 };
 
 // Launchers (xrt_kernels.hip).  All enqueue on `s` and return the launch status.
 hipError_t launch_canon(const CanonArgs& a, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
 int64_t scan_tmp_words(int64_t n);
-hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
+int64_t radix_tmp_words(int64_t m, int64_t max_key);
+hipError_t launch_radix_sort(const SortArgs& a, hipStream_t s);
 hipError_t launch_header(PlanHeader* hdr, const uint32_t* off, int64_t vert_end, int64_t valid_end,
                          hipStream_t s);
 hipError_t launch_forward(const xrt_plan* p, const float* coeffs, float* sino, hipStream_t s);
 hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipStream_t s);
+// NaN into every pixel of the support of each line whose value in sw (a
+// plan's sorted, scaled sinogram) is NaN or infinite
+hipError_t launch_adj_nonfinite(const xrt_plan* p, const float* sw, float* out, hipStream_t s);
 hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s);
 
 // xrt_plan_create; own_buffers = false leaves out the buffers that only the
@@ -117,6 +147,8 @@ hipError_t launch_batch_fwd_reduce(const void* probs, int p, int64_t m, hipStrea
 hipError_t launch_layouts(const xrt_plan* p, const float* coeffs, hipStream_t s);
 hipError_t launch_sort_sino(const xrt_plan* p, const float* sino, hipStream_t s);
 hipError_t launch_reset_counters(unsigned int* c, int n, hipStream_t s);
+// non-finite sinogram values of every problem (after both adjoint launches)
+hipError_t launch_batch_nonfinite(const void* probs, int count, int64_t max_m, hipStream_t s);
 hipError_t launch_batch_forward(const void* probs, const int2* items, int nitems, unsigned int* counter,
                                 int lines_per_item, int grid, hipStream_t s);
 // horizontal = 0: the vertical lines on kTileI x kTileJ tiles (writes the

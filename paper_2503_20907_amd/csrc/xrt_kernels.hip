@@ -43,6 +43,7 @@
 // with its own row arithmetic (box_row, box_F): a telescoped row sum over two
 // or four columns instead of taps and knots.
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -230,14 +231,90 @@ __global__ void __launch_bounds__(kBlock) k_scan_add(uint32_t* out, const uint32
 }
 
 
-__global__ void __launch_bounds__(kBlock) k_scatter(ScatterArgs A)
+// Stable LSD radix sort of the plan keys, 8 bits per pass: the lines of one
+// key keep their input order, so a plan (and every result computed with it)
+// depends only on the line list.  Each workgroup owns kRsTile consecutive
+// elements; k_rs_hist counts its digits, an exclusive scan of the
+// digit-major table [digit][workgroup] gives every (digit, workgroup) its
+// first output position, and k_rs_scatter places the elements in input
+// order: rounds of kBlock elements, ranks within a wave from a match of the
+// 8 digit bits over ballots, then the counts of the earlier waves.
+constexpr int kRsPer = 16;
+constexpr int kRsTile = kBlock * kRsPer;
+static_assert(kBlock == 256, "one digit per thread");
+
+__global__ void __launch_bounds__(kBlock) k_rs_hist(const uint32_t* __restrict__ key, int64_t m, int shift,
+                                                  uint32_t* __restrict__ hist, int nblk)
 {
-    int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (m >= A.m) return;
-    uint32_t pos = atomicAdd(&A.cursor[A.key[m]], 1u);
-    A.xc[pos] = A.xc_in[m];
-    A.kap[pos] = A.kap_in[m];
-    A.idx[pos] = (int32_t)m;
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsPer; ++r) {
+        const int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < m) atomicAdd(&cnt[(key[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBlock) k_rs_scatter(RadixArgs A)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    run[tid] = A.hoff[(int64_t)tid * A.nblk + blockIdx.x];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wc[v][tid] = 0;
+    __syncthreads();
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsPer; ++r) {
+        const int64_t i = base + r * kBlock + tid;
+        const bool valid = i < A.m;
+        uint32_t k = 0, v = 0, d = 0;
+        if (valid) {
+            k = A.key_in[i];
+            v = A.val_in ? A.val_in[i] : (uint32_t)i;
+            d = (k >> A.shift) & 255u;
+        }
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int u = 0; u < w; ++u) pos += wc[u][d];
+            A.key_out[pos] = k;
+            A.val_out[pos] = v;
+        }
+        __syncthreads();
+        run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) wc[u][tid] = 0;
+        __syncthreads();
+    }
+}
+
+// sorted position -> line records of the line it holds
+__global__ void __launch_bounds__(kBlock) k_rs_gather(const uint32_t* __restrict__ val,
+                                                    const double* __restrict__ xc_in,
+                                                    const double* __restrict__ kap_in, double* __restrict__ xc,
+                                                    double* __restrict__ kap, int32_t* __restrict__ idx, int64_t m)
+{
+    const int64_t pos = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pos >= m) return;
+    const uint32_t l = val[pos];
+    xc[pos] = xc_in[l];
+    kap[pos] = kap_in[l];
+    idx[pos] = (int32_t)l;
 }
 
 __global__ void k_header(PlanHeader* hdr, const uint32_t* off, int64_t vert_end, int64_t valid_end)
@@ -367,8 +444,14 @@ __device__ inline f4v tab_at(const float4* tab, uint32_t byte)
 }
 __device__ inline f4v tab_at(const GTab* tab, uint32_t byte) { return *(const GTab*)((const GByte*)tab + byte); }
 
+// For even n, E jumps at 0 (by P(0): 1 for n = 0, 1/8 for n = 2), and the
+// jump cancels the one of the taps at the same knot.  Which side of the knot
+// the row lies on must therefore be the side the taps take, J = floor(q) in
+// FP64: `right` (q >= K, i.e. z >= 0) comes from the slot's integer offset,
+// not from the sign of the FP32 argument, which rounds to 0 when q lies
+// within ~1e-8 below K (the fraction of q then rounds to 1.0f).
 template <int N, typename T>
-__device__ inline float etab(const T* __restrict__ tab, float zt)
+__device__ inline float etab(const T* __restrict__ tab, float zt, bool right)
 {
     constexpr int last = kTabPerUnit * (N + 1) / 2;  // index of the zero interval
     const float a = fminf(fabsf(zt), (float)last);
@@ -376,7 +459,7 @@ __device__ inline float etab(const T* __restrict__ tab, float zt)
     const float tau = __builtin_amdgcn_fractf(a);
     const f4v cf = tab_at(tab, (uint32_t)i << 4);
     float g = fmaf(tau, fmaf(tau, fmaf(tau, cf.w, cf.z), cf.y), cf.x);
-    if constexpr (N % 2 == 0) g = zt >= 0.f ? -g : g;
+    if constexpr (N % 2 == 0) g = right ? -g : g;
     return g;
 }
 
@@ -419,13 +502,14 @@ __device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>
         oz = (float)o * k.inv_tab;
     }
     R.K0 = R.J + o;
-    // z_s = (q - K0 - s) / r, in table units
+    // z_s = (q - K0 - s) / r, in table units; knot K0 + s lies at or left of
+    // q (z_s >= 0) exactly when o + s <= 0
     const float a0 = fmaf(t, k.inv_tab, -oz);
-    R.g[0] = G > 0 ? etab<N>(tab.mem, a0) : etab<N>(tab.lds, a0);
+    R.g[0] = G > 0 ? etab<N>(tab.mem, a0, o <= 0) : etab<N>(tab.lds, a0, o <= 0);
 #pragma unroll
     for (int sl = 1; sl < S; ++sl) {
         const float z = fmaf(-(float)sl, k.inv_tab, a0);
-        R.g[sl] = sl < G ? etab<N>(tab.mem, z) : etab<N>(tab.lds, z);
+        R.g[sl] = sl < G ? etab<N>(tab.mem, z, o + sl <= 0) : etab<N>(tab.lds, z, o + sl <= 0);
     }
 }
 
@@ -1312,6 +1396,9 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                     kk[u] = s_start[lo] + (item - s_pre[lo]);
                     svv[u] = A.sw[kk[u]];
                 }
+                // a NaN or infinite value is left out here (it would break
+                // the chunk's scale); k_adj_nonfinite marks its pixels
+                if (!(fabsf(svv[u]) <= FLT_MAX)) svv[u] = 0.f;
                 amax = fmaxf(amax, fabsf(svv[u]));
             }
             const float mx = block_max(amax, s_red);
@@ -1386,6 +1473,41 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
     adj_tile<N, MODE>(A, tile, (int)blockIdx.y, sh);
 }
 
+// Lines whose (sorted, scaled) sinogram value is NaN or infinite: the
+// adjoint's fixed-point sums leave them out, and every pixel inside the
+// line's footprint support, |X(j) - i| < W in each row j it reaches, is set
+// to NaN here, after both passes.  W is the support half-width in minor
+// cells: (n+1)(1 + |kappa|)/2 for the B-splines, 1 (kappa >= 0) or
+// 1 + |kappa| for the box spline.
+__device__ inline void adj_nonfinite_line(const NonFiniteArgs& A, int64_t k)
+{
+    if (k >= A.m) return;
+    if (fabsf(A.sw[k]) <= FLT_MAX) return;
+    if (k >= A.hdr->m_valid) return;
+    const bool vert = k < A.hdr->m_vert;
+    const int nmaj = vert ? A.ny : A.nx, nmin = vert ? A.nx : A.ny;
+    const double kap = A.kap[k];
+    const double x0 = A.xc[k] - kap * (0.5 * (nmaj - 1));
+    const double W = A.box ? (kap >= 0.0 ? 1.0 : 1.0 - kap) : 0.5 * (A.degree + 1) * (1.0 + fabs(kap));
+    int jlo, jhi;
+    row_range(x0, kap, 1.0 / kap, W, nmaj, nmin, &jlo, &jhi);
+    const float nan = __int_as_float(0x7fc00000);
+    for (int j = jlo; j <= jhi; ++j) {
+        const double X = x0 + kap * (double)j;
+        const int lo = (int)fmax(floor(X - W) + 1.0, 0.0);
+        const int hi = (int)fmin(ceil(X + W) - 1.0, (double)(nmin - 1));
+        for (int i = lo; i <= hi; ++i) {
+            const int64_t pix = vert ? (int64_t)j * A.nx + i : (int64_t)i * A.nx + j;
+            A.out[pix] = nan;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_adj_nonfinite(NonFiniteArgs A)
+{
+    adj_nonfinite_line(A, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
 // out (+)= sum over the split workgroups' partial images, in a fixed order
 __global__ void __launch_bounds__(kBlock) k_adj_reduce(const float* part, int split, int64_t npix, int accumulate,
                                                        float* out)
@@ -1407,6 +1529,7 @@ struct BatchProb {
     int nstrip;     // strips of kStrip rows (the larger of the two orientations)
     int64_t m_vert, m_valid;
     float* spart;   // [nstrip][m] per-strip line sums (unscaled)
+    NonFiniteArgs nf;  // lines with a non-finite sinogram value (after the adjoint)
 };
 struct BatchArgs {
     const BatchProb* probs;
@@ -1618,11 +1741,62 @@ int64_t scan_tmp_words(int64_t n)
     return w + 16;
 }
 
-hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s)
+int64_t radix_tmp_words(int64_t m, int64_t max_key)
+{
+    const int64_t nblk = (m + kRsTile - 1) / kRsTile;
+    const int64_t nh = 256 * nblk;
+    (void)max_key;
+    // key and value ping-pong buffers, the digit table and its scan
+    return 3 * m + 2 * nh + 1 + scan_tmp_words(nh);
+}
+
+hipError_t launch_radix_sort(const SortArgs& a, hipStream_t s)
 {
     if (a.m == 0) return hipSuccess;
+    int bits = 0;
+    while (bits < 32 && (a.max_key >> bits) != 0) ++bits;
+    const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+    const int64_t nblk = (a.m + kRsTile - 1) / kRsTile;
+    const int64_t nh = 256 * nblk;
+    uint32_t* key2 = a.tmp;
+    uint32_t* val1 = key2 + a.m;
+    uint32_t* val2 = val1 + a.m;
+    uint32_t* hist = val2 + a.m;
+    uint32_t* hoff = hist + nh;
+    uint32_t* stmp = hoff + nh + 1;
+    const uint32_t* kin = a.key;
+    const uint32_t* vin = nullptr;  // the first pass numbers the lines itself
+    uint32_t* kout = key2;
+    uint32_t* vout = val1;
+    uint32_t* kspare = a.key;
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nblk), dim3(kBlock), 0, s, kin, a.m, 8 * p, hist, (int)nblk);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_scan(hist, hoff, nh, stmp, s);
+        if (e != hipSuccess) return e;
+        RadixArgs ra;
+        ra.key_in = kin;
+        ra.val_in = vin;
+        ra.key_out = kout;
+        ra.val_out = vout;
+        ra.m = a.m;
+        ra.shift = 8 * p;
+        ra.hoff = hoff;
+        ra.nblk = (int)nblk;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nblk), dim3(kBlock), 0, s, ra);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // the output becomes the next input; the old input's buffers take the next output
+        uint32_t* knext = kspare;
+        kspare = kout;
+        kin = kout;
+        kout = knext;
+        vin = vout;
+        vout = vout == val1 ? val2 : val1;
+    }
     dim3 grid((unsigned)((a.m + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(k_scatter, grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rs_gather, grid, dim3(kBlock), 0, s, vin, a.xc_in, a.kap_in, a.xc, a.kap, a.idx, a.m);
     return hipGetLastError();
 }
 
@@ -1777,12 +1951,38 @@ static hipError_t adjoint_pass(const xrt_plan* p, float* out, hipStream_t s)
     return hipGetLastError();
 }
 
+static NonFiniteArgs make_nonfinite_args(const xrt_plan* p, const float* sw, float* out)
+{
+    NonFiniteArgs a;
+    a.m = p->m;
+    a.hdr = p->hdr;
+    a.xc = p->xc;
+    a.kap = p->kap;
+    a.sw = sw;
+    a.nx = p->g.nx;
+    a.ny = p->g.ny;
+    a.degree = geom_degree(p->degree);
+    a.box = p->degree == kBox3 ? 1 : 0;
+    a.out = out;
+    return a;
+}
+
+hipError_t launch_adj_nonfinite(const xrt_plan* p, const float* sw, float* out, hipStream_t s)
+{
+    if (p->m == 0) return hipSuccess;
+    const NonFiniteArgs a = make_nonfinite_args(p, sw, out);
+    hipLaunchKernelGGL(k_adj_nonfinite, dim3((unsigned)((p->m + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int N>
 static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
 {
     hipError_t e = adjoint_pass<N, kAdjVert>(p, out, s);
     if (e != hipSuccess) return e;
-    return adjoint_pass<N, kAdjHoriz>(p, out, s);
+    e = adjoint_pass<N, kAdjHoriz>(p, out, s);
+    if (e != hipSuccess) return e;
+    return launch_adj_nonfinite(p, p->sw, out, s);
 }
 
 static hipError_t sort_sino(const xrt_plan* p, const float* sino, hipStream_t s)
@@ -1849,6 +2049,7 @@ void batch_fill(const xrt_plan* p, float* sino, float* back, float* spart, void*
     b.m_vert = p->m_vert;
     b.m_valid = p->m_valid;
     b.spart = spart;
+    b.nf = make_nonfinite_args(p, p->sw, back);
     memcpy(dst, &b, sizeof(b));
 }
 
@@ -1873,6 +2074,20 @@ hipError_t launch_layouts(const xrt_plan* p, const float* coeffs, hipStream_t s)
 }
 
 hipError_t launch_sort_sino(const xrt_plan* p, const float* sino, hipStream_t s) { return sort_sino(p, sino, s); }
+
+// k_adj_nonfinite over every problem of a batch (blockIdx.y = problem)
+__global__ void __launch_bounds__(kBlock) k_batch_nonfinite(const BatchProb* probs)
+{
+    adj_nonfinite_line(probs[blockIdx.y].nf, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
+hipError_t launch_batch_nonfinite(const void* probs, int count, int64_t max_m, hipStream_t s)
+{
+    if (max_m == 0 || count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_nonfinite, dim3((unsigned)((max_m + kBlock - 1) / kBlock), (unsigned)count),
+                       dim3(kBlock), 0, s, static_cast<const BatchProb*>(probs));
+    return hipGetLastError();
+}
 
 hipError_t launch_reset_counters(unsigned int* c, int n, hipStream_t s)
 {
