@@ -31,20 +31,27 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "xrt_oracle.c")
-_LIB = os.path.join(_HERE, "liborc.so")
+# XRT_ORACLE_LIB names another build of the same source (the sanitizer
+# build of tests/test_sanitizers.py); by default the library built here
+_LIB = os.environ.get("XRT_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined,float-cast-overflow",
+                  "-fno-sanitize-recover=all"]
 
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (IEEE FP64, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-o", tmp, _SRC, "-lm"]
+def build(force: bool = True, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (IEEE FP64, OpenMP); with sanitize, with
+    AddressSanitizer and UndefinedBehaviorSanitizer (into `out`)."""
+    lib = out or _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+        cmd = ["gcc"] + opt + ["-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                               "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Grid(ctypes.Structure):

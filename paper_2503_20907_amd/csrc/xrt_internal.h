@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "xrt.h"
+#include "xrt_geom.h"
 
 namespace xrt {
 
@@ -21,22 +22,6 @@ constexpr int kSlopeBins = 512;
 constexpr int kTabPerUnit = 16;
 // Largest table: degree 3, half-support 2 -> 32 intervals + 1 zero interval.
 constexpr int kTabMax = kTabPerUnit * 2 + 1;
-// Adjoint tile (pixels): kTileI columns (x1) by kTileJ rows (x2) for the
-// vertical lines, and the transposed tile for the horizontal ones (kTileI
-// across the lines either way).  64 x 32 measured fastest among 16..128-pixel
-// tile sides on the 2048^2 cubic workload.
-#ifndef XRT_TILE_I
-#define XRT_TILE_I 64
-#endif
-#ifndef XRT_TILE_J
-#define XRT_TILE_J 32
-#endif
-constexpr int kTileI = XRT_TILE_I;
-constexpr int kTileJ = XRT_TILE_J;
-// Halo (cells) of the LDS accumulators of the adjoint on each minor side:
-// with crossings kept within n+1 cells of the tile, taps and knot slots stay
-// within 7 cells (degree 3) of it.
-constexpr int kHalo = 8;
 constexpr int kBlock = 256;
 // Rows per strip of the forward's strip-major schedule (one strip of the
 // coefficient layouts, about 2 MB at 2048 columns, stays in an XCD's L2).
@@ -53,10 +38,6 @@ struct PlanHeader {
     int64_t pad;
 };
 
-struct GridGeom {
-    int nx, ny;
-    double h, cx, cy;
-};
 
 
 struct LineIn {

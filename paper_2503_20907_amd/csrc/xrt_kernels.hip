@@ -56,20 +56,12 @@ typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
 
 // ---------------------------------------------------------------- geometry
-struct Canon {
-    double xc;   // crossing at the centre major index
-    double kap;  // slope
-    int cls;     // 0 vertical, 1 horizontal, 2 misses the padded grid
-    int bad;     // degenerate / non-finite input
-};
-
 
 // Line (theta, y) of eq. (1) in world coordinates -> index space of the grid,
 // then to the crossing form minor = X0 + kappa * major.
 __device__ inline Canon canonicalize(const LineIn& L, int64_t m, const GridGeom& g, int degree)
 {
-    Canon o;
-    o.bad = 0;
+    int bad = 0;
     double c, s, yw;
     if (L.kind == XRT_LINES_ENDPOINTS) {
         double px = L.ep[4 * m + 0], py = L.ep[4 * m + 1];
@@ -77,7 +69,7 @@ __device__ inline Canon canonicalize(const LineIn& L, int64_t m, const GridGeom&
         double dx = qx - px, dy = qy - py;
         double len = sqrt(dx * dx + dy * dy);
         if (!(len > 0.0) || !isfinite(len) || !isfinite(px) || !isfinite(py)) {
-            o.bad = 1;
+            bad = 1;
             len = 1.0;
             dx = 1.0;
             dy = 0.0;
@@ -89,58 +81,13 @@ __device__ inline Canon canonicalize(const LineIn& L, int64_t m, const GridGeom&
         double t = (double)L.theta[m];
         yw = (double)L.y[m];
         if (!isfinite(t) || !isfinite(yw)) {
-            o.bad = 1;
+            bad = 1;
             t = 0.0;
             yw = 0.0;
         }
         sincos(t, &s, &c);
     }
-    // i*s - j*c = Y in index space
-    const double ox = 0.5 * (g.nx - 1), oy = 0.5 * (g.ny - 1);
-    const double Y = (yw - (g.cx * s - g.cy * c)) / g.h + ox * s - oy * c;
-    const bool vert = fabs(s) >= fabs(c);
-    const int nmaj = vert ? g.ny : g.nx, nmin = vert ? g.nx : g.ny;
-    double X0, kap;
-    if (vert) {
-        X0 = Y / s;
-        kap = c / s;
-    } else {
-        X0 = -Y / c;
-        kap = s / c;
-    }
-    const double jc = 0.5 * (nmaj - 1);
-    o.xc = X0 + kap * jc;
-    o.kap = kap;
-    // rows whose band reaches the grid: -W < X(j) < nmin - 1 + W
-    const double W = 0.5 * (degree + 1) * (1.0 + fabs(kap));
-    bool hit;
-    if (kap == 0.0) {
-        hit = X0 > -W && X0 < nmin - 1 + W;
-    } else {
-        double a = (-W - X0) / kap, b = (nmin - 1 + W - X0) / kap;
-        double lo = fmin(a, b), hi = fmax(a, b);
-        hit = hi > 0.0 && lo < (double)(nmaj - 1);
-    }
-    o.cls = o.bad ? 2 : (hit ? (vert ? 0 : 1) : 2);
-    return o;
-}
-
-// Rows [jlo, jhi] (closed) of a line whose band may reach the grid.
-// inv = 1/kap (unused when kap = 0); a product with it instead of a
-// quotient moves the bounds by ~1e-16 relative, far inside the 1e-9 slack
-__device__ inline void row_range(double x0, double kap, double inv, double W, int nmaj, int nmin, int* jlo,
-                                 int* jhi)
-{
-    if (kap == 0.0) {
-        *jlo = 0;
-        *jhi = nmaj - 1;
-        return;
-    }
-    double a = (-W - x0) * inv, b = (nmin - 1 + W - x0) * inv;
-    double lo = fmin(a, b), hi = fmax(a, b);
-    double flo = ceil(lo - 1e-9), fhi = floor(hi + 1e-9);
-    *jlo = (int)fmax(0.0, flo);
-    *jhi = (int)fmin((double)(nmaj - 1), fhi);
+    return canon_core(c, s, yw, g, degree, bad);
 }
 
 __device__ inline int slope_bin(double kap)
@@ -487,7 +434,7 @@ __device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>
 {
     // q > 0 here (a padded or halo-relative column coordinate), so truncation
     // is the floor
-    const float t = (float)__builtin_amdgcn_fract(q);
+    const float t = (float)frac_pos(q);
     R.J = (int)q;
     R.t = t;
     // the S knots nearest to q: centred on round(q) for odd S, on q for even S
@@ -950,7 +897,7 @@ struct AdjArgs {
 // wave update fall into different LDS banks; an accumulator holds the
 // tile's kTileJ rows along the lines, each kTileI wide across them, plus
 // halos
-constexpr int kAccWords = kTileJ * (kTileI + 2 * kHalo + 1);
+constexpr int kAccWords = kTileJ * kAccPitch;
 constexpr int kPix = kTileI * kTileJ / kBlock;
 // every thread flushes kPix whole pixels, and the candidate scan takes the
 // slope bins two per thread
@@ -1097,9 +1044,8 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     int jj = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
     const float svkr = svk * lc.rn;
     const TapScaled<N> tk = tap_scaled<N>(svs, lc.rho);
-    // knot slots start at K0 = J + o, o = 1 - S/2 for even S (a constant), so
-    // that taps and slots share one base address at J - N
-    constexpr int kEven = 1 - S / 2 + N;
+    // knot slots start at K0 = J + o (o = 1 - S/2 for even S, a constant),
+    // so that taps and slots share one base address at J - N
     // walk q - N (exact): its floor is the first tap J - N (at least 0: the
     // halo covers the footprint), which is the base address of the row
     const double q0n = q0 - (double)N;
@@ -1111,9 +1057,9 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
         row_core<N, S, adj_mem_slots<N, S, L1>()>(q, lc, s_tab, R);
         int wi[N + 1];
         tap_fixed<N>(R.t, tk, wi);
-        const uint32_t base = __umul24((uint32_t)(row0 + jj), (uint32_t)W) + (uint32_t)R.J;
+        const uint32_t base = adj_tap_base(row0 + jj, W, R.J);
         int* ar = s_a + base;  // taps J-N .. J, ascending
-        int* kr = s_k + base + (S % 2 == 0 ? (uint32_t)kEven : (uint32_t)(R.K0 - R.J + N));
+        int* kr = s_k + base + (uint32_t)adj_knot_offset<N, S>(R.t);
 #pragma unroll
         for (int d = 0; d <= N; ++d) atomicAdd(ar + d, wi[N - d]);
 #pragma unroll
@@ -1137,8 +1083,8 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
         // q > 0 (halo-relative column), so truncation is the floor
         const double q = fma(kap, (double)jj, q0);
         const float t = (float)__builtin_amdgcn_fract(q);
-        const uint32_t rb = __umul24((uint32_t)(row0 + jj), (uint32_t)W);
-        int* ar = s_a + (rb + (uint32_t)((int)q - 1));
+        // columns floor(q) - 1 .. floor(q) + 2
+        int* ar = s_a + adj_tap_base(row0 + jj, W, (int)q - 1);
         if constexpr (NEG) {
             // kappa < 0: 1 - F_0 = k0 p^2 is formed directly
             const float p = fmaxf(bk.a - t, 0.f), qq = fmaxf(t + bk.am1, 0.f);
@@ -1161,28 +1107,18 @@ __device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, f
                                     int min0, int TM, int TN, int nmaj, int W, double jc, double marg, int* s_a)
 {
     if (!active) return;
-    const double xc = A.xc[k], kap = A.kap[k];
-    const double x0 = xc - kap * jc;
+    const double kap = A.kap[k];
     const int nmin = vert ? A.nx : A.ny;
-    int jlo, jhi;
     // rows whose crossing lies within the footprint's half-width (1 for
     // kappa >= 0, 1 + |kappa| otherwise; at most marg) of the tile
     const double ml = kap >= 0.0 ? 1.0 : 1.0 - kap;
-    const double inv = 1.0 / kap;
-    row_range(x0, kap, inv, ml, nmaj, nmin, &jlo, &jhi);
-    int ra = max(jlo, maj0), rb = min(jhi, maj0 + TM - 1);
-    if (kap != 0.0) {
-        double a = (min0 - ml - x0) * inv, b = (min0 + TN - 1 + ml - x0) * inv;
-        double lo2 = fmin(a, b), hi2 = fmax(a, b);
-        ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
-        rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
-    } else if (!(x0 >= min0 - ml && x0 <= min0 + TN - 1 + ml)) {
-        return;
-    }
+    const AdjRows rr = adj_rows(A.xc[k], kap, jc, ml, nmaj, nmin, maj0, min0, TM, TN);
+    const int ra = rr.ra, rb = rr.rb;
+    const double x0 = rr.x0;
     (void)marg;
     if (ra > rb) return;
     const BoxRow bk = box_row(kap);
-    const double q0 = x0 + kap * (double)ra - (double)min0 + (double)kHalo;
+    const double q0 = adj_q0(x0, kap, ra, min0, 0.0);
     if (bk.neg) adj_walk_box<true>(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
     else adj_walk_box<false>(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
 }
@@ -1197,26 +1133,14 @@ __device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float
     int ra = 0, rb = -1;
     double kap = 0.0, x0 = 0.0;
     if (active) {
-        const double xc = A.xc[k];
         kap = A.kap[k];
-        x0 = xc - kap * jc;
         const int nmin = vert ? A.nx : A.ny;
-        int jlo, jhi;
         // rows whose crossing lies within the footprint's half-width
         // H (1 + |kappa|) of the tile (at most marg)
-        const double ml = H * (1.0 + fabs(kap));
-        const double inv = 1.0 / kap;
-        row_range(x0, kap, inv, ml, nmaj, nmin, &jlo, &jhi);
-        ra = max(jlo, maj0);
-        rb = min(jhi, maj0 + TM - 1);
-        if (kap != 0.0) {
-            double a = (min0 - ml - x0) * inv, b = (min0 + TN - 1 + ml - x0) * inv;
-            double lo2 = fmin(a, b), hi2 = fmax(a, b);
-            ra = max(ra, (int)fmin(fmax(ceil(lo2 - 1e-9), -1.0e9), 1.0e9));
-            rb = min(rb, (int)fmin(fmax(floor(hi2 + 1e-9), -1.0e9), 1.0e9));
-        } else if (!(x0 >= min0 - ml && x0 <= min0 + TN - 1 + ml)) {
-            rb = ra - 1;
-        }
+        const AdjRows rr = adj_rows(A.xc[k], kap, jc, H * (1.0 + fabs(kap)), nmaj, nmin, maj0, min0, TM, TN);
+        ra = rr.ra;
+        rb = rr.rb;
+        x0 = rr.x0;
     }
     (void)marg;
     const bool work = active && ra <= rb;
@@ -1226,7 +1150,7 @@ __device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float
     const float svs = ldexpf(sv, e);
     const float svk = ldexpf(sv, e + knot_shift<N>());
     // local q: column index within the LDS row (halo included)
-    const double q0 = x0 + kap * (double)ra + H - (double)min0 + (double)kHalo;
+    const double q0 = adj_q0(x0, kap, ra, min0, H);
     const int cnt = rb - ra + 1, row0 = ra - maj0;
     if (S == 1) adj_walk<N, 1, L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
     else if (S == 2) adj_walk<N, (N >= 1 ? 2 : 1), L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
@@ -1312,7 +1236,8 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
         const int maj0 = vert ? j0 : i0, min0 = vert ? i0 : j0;
         const int TM = vert ? TJ : TI, TN = vert ? TI : TJ;
         const int nmaj = vert ? A.ny : A.nx;
-        const int W = TN + 2 * kHalo + 1;  // odd pitch
+        const int W = TN + 2 * kHalo + 1;  // odd pitch (kAccPitch)
+        static_assert(adj_ti<MODE>() == kTileI || adj_tj<MODE>() == kTileI, "kTileI across the lines");
         const int nbk = vert ? A.nbk_v : A.nbk_h;
         const int boff = vert ? A.boff_v : A.boff_h;
         const uint32_t cls_base = vert ? 0u : (uint32_t)kSlopeBins * (uint32_t)A.nbk_v;
