@@ -108,6 +108,23 @@ xrt_status xrt_forward(const float* coeffs, xrt_grid g, int degree, const xrt_li
 xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xrt_grid g,
                        float* coeffs_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * adjoint of xrt_adjoint, same arguments, same result bit for bit, with no
+ * device allocation or free and no synchronisation.  Its temporary plan
+ * lives in one static device array of 64 MiB that each GPU the library runs
+ * on holds until the process ends (about 56 B per line, 8 B per
+ * (orientation, slope bin, crossing bucket) key and up to 8 partial images:
+ * e.g. 700,000 lines on a 512^2 grid); larger problems return XRT_ESIZE.
+ * The first call on a device sets the array up (looks up its address and
+ * uploads the footprint tables, synchronously).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU race and must be
+ * serialised by the caller.  Degenerate or non-finite lines are not
+ * reported (that needs a synchronisation); they contribute nothing.
+ * Use xrt_plan_create to validate a line list. */
+xrt_status xrt_adjoint_noalloc(const float* sino, const xrt_lines* lines, int degree, xrt_grid g,
+                               float* coeffs_out, void* stream);
+
 /* Builds a plan for (grid, degree, lines).  The line arrays are read during
  * the call only.  On error *out is NULL and nothing stays allocated.
  * Device memory held by the plan: about 24 B per line (sorted line records,
@@ -119,11 +136,9 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
                            xrt_plan** out);
 
 /* Forward / adjoint with a plan: the hot path.  No synchronisation, no
- * allocation.  Repeated calls with one plan give bitwise-identical results.
- * Two plans built from the same lines can order the lines of a bucket
- * differently (the plan's counting sort scatters with atomics).  The forward
- * does not depend on that order; the adjoint's fixed-point rounding does, by
- * about one FP32 rounding (1e-7 relative). */
+ * allocation.  Repeated calls with one plan give bitwise-identical results,
+ * and so do two plans built from the same lines (the plan's sort is stable:
+ * lines of one bucket keep their input order). */
 xrt_status xrt_plan_forward(const xrt_plan* p, const float* coeffs, float* sino, void* stream);
 xrt_status xrt_plan_adjoint(const xrt_plan* p, const float* sino, float* coeffs_out,
                             void* stream);

@@ -32,7 +32,7 @@ EXPORTS = (
     # xrt.h
     "xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward", "xrt_plan_adjoint",
     "xrt_plan_info", "xrt_plan_nnz", "xrt_plan_destroy", "xrt_status_string", "xrt_last_error",
-    "xrt_version",
+    "xrt_version", "xrt_adjoint_noalloc",
     # xrt_learn.h
     "xrt_reg_apply", "xrt_normal_apply", "xrt_unet_create", "xrt_unet_destroy", "xrt_unet_num_params",
     "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_set_gain", "xrt_unet_get_gain",
@@ -106,6 +106,7 @@ def load() -> ctypes.CDLL:
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     lib.xrt_forward.argtypes = [vp, XrtGrid, i32, ctypes.POINTER(XrtLines), vp, vp]
     lib.xrt_adjoint.argtypes = [vp, ctypes.POINTER(XrtLines), i32, XrtGrid, vp, vp]
+    lib.xrt_adjoint_noalloc.argtypes = [vp, ctypes.POINTER(XrtLines), i32, XrtGrid, vp, vp]
     lib.xrt_plan_create.argtypes = [XrtGrid, i32, ctypes.POINTER(XrtLines), vp,
                                     ctypes.POINTER(vp)]
     lib.xrt_plan_forward.argtypes = [vp, vp, vp, vp]
@@ -162,7 +163,7 @@ def load() -> ctypes.CDLL:
                  "xrt_batch_adjoint", "xrt_batch_run", "xrt_batch_get_config", "xrt_batch_set_config",
                  "xrt_batch_autotune"):
         getattr(lib, name).restype = i32
-    for name in ("xrt_forward", "xrt_adjoint", "xrt_plan_create", "xrt_plan_forward",
+    for name in ("xrt_forward", "xrt_adjoint", "xrt_adjoint_noalloc", "xrt_plan_create", "xrt_plan_forward",
                  "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_reg_apply",
                  "xrt_normal_apply", "xrt_unet_create", "xrt_unet_num_params",
                  "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_apply",
@@ -184,7 +185,7 @@ def last_error() -> str:
 
 def check(st: int, where: str):
     if st != XRT_OK:
-        raise XrtError(st, where, last_error() if st in (XRT_EHIP, XRT_ENOMEM) else "")
+        raise XrtError(st, where, last_error() if st in (XRT_EHIP, XRT_ENOMEM, XRT_ESIZE) else "")
 
 
 def xrt_forward(coeffs, grid: XrtGrid, degree: int, lines: XrtLines, sino, stream) -> int:
@@ -193,6 +194,10 @@ def xrt_forward(coeffs, grid: XrtGrid, degree: int, lines: XrtLines, sino, strea
 
 def xrt_adjoint(sino, lines: XrtLines, degree: int, grid: XrtGrid, coeffs_out, stream) -> int:
     return load().xrt_adjoint(sino, ctypes.byref(lines), int(degree), grid, coeffs_out, stream)
+
+
+def xrt_adjoint_noalloc(sino, lines: XrtLines, degree: int, grid: XrtGrid, coeffs_out, stream) -> int:
+    return load().xrt_adjoint_noalloc(sino, ctypes.byref(lines), int(degree), grid, coeffs_out, stream)
 
 
 def xrt_plan_create(grid: XrtGrid, degree: int, lines: XrtLines, stream):

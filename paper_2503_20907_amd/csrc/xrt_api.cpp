@@ -195,20 +195,16 @@ xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void*
 }  // extern "C"
 
 namespace xrt {
-xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool own_buffers,
-                       xrt_plan** out)
+xrt_status plan_check(xrt_grid g, int degree, const xrt_lines* lines)
 {
-    if (!out) return XRT_EINVAL;
-    *out = nullptr;
     if (!valid_basis(degree)) return XRT_EDEGREE;
     xrt_status st = check_grid(g);
     if (st != XRT_OK) return st;
-    st = check_lines(lines);
-    if (st != XRT_OK) return st;
+    return check_lines(lines);
+}
 
-    hipStream_t s = (hipStream_t)stream;
-    xrt_plan* p = new (std::nothrow) xrt_plan;
-    if (!p) return XRT_ENOMEM;
+void plan_init(xrt_plan* p, xrt_grid g, int degree, int64_t m, bool split_tiles)
+{
     memset(p, 0, sizeof(*p));
     p->magic = kPlanMagic;
     p->g.nx = g.nx;
@@ -217,7 +213,7 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     p->g.cx = g.cx;
     p->g.cy = g.cy;
     p->degree = degree;
-    p->m = lines->n;
+    p->m = m;
     // crossing buckets: floor(Xc) + boff in [0, nbk) for every line that
     // reaches the grid (|Xc| <= nmin + nmaj/2 + (n+1))
     p->boff_v = (g.ny + 1) / 2 + 8;
@@ -230,6 +226,82 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     p->pitch_h = round_up(g.ny + 2 * kPad, 16);
     p->strips_v = (g.ny + kStrip - 1) / kStrip;
     p->strips_h = (g.nx + kStrip - 1) / kStrip;
+    // split each adjoint tile's candidate lines over up to 8 workgroups
+    // (partial images, summed in a fixed order), aiming at kAdjUnits
+    // workgroups per pass: with few units per compute unit the tiles that
+    // finish last leave it partly idle (2048^2: 2048 tiles per pass, cubic
+    // adjoint 27.9 ms unsplit, 25.4 ms split 6 ways)
+    const int64_t tiles = (int64_t)((g.nx + kTileI - 1) / kTileI) * ((g.ny + kTileJ - 1) / kTileJ);
+    p->adj_split = split_tiles ? (int)std::min<int64_t>(8, (kAdjUnits + tiles - 1) / tiles) : 1;
+}
+
+hipError_t plan_build(const xrt_plan* p, const xrt_lines* lines, const PlanTemps& t, hipStream_t s,
+                      const char** what)
+{
+    hipError_t e = hipSuccess;
+#define XRT_TRY(call, label)                   \
+    do {                                       \
+        if (e == hipSuccess) {                 \
+            e = (call);                        \
+            if (e != hipSuccess) *what = label; \
+        }                                      \
+    } while (0)
+    const int64_t per_v = (int64_t)kSlopeBins * p->nbk_v, per_h = (int64_t)kSlopeBins * p->nbk_h;
+    // cleared by a kernel (no memset node if a caller captures the stream)
+    XRT_TRY(launch_fill_u32(t.count, p->key_space, 0u, s), "clear");
+    XRT_TRY(launch_fill_u32((uint32_t*)p->hdr, sizeof(PlanHeader) / 4, 0u, s), "clear");
+    CanonArgs ca;
+    ca.L.kind = lines->kind;
+    ca.L.theta = lines->theta;
+    ca.L.y = lines->y;
+    ca.L.ep = lines->endpoints;
+    ca.m = p->m;
+    ca.g = p->g;
+    ca.degree = geom_degree(p->degree);
+    ca.nbk_v = p->nbk_v;
+    ca.nbk_h = p->nbk_h;
+    ca.boff_v = p->boff_v;
+    ca.boff_h = p->boff_h;
+    ca.key = t.key;
+    ca.xc = t.xc_in;
+    ca.kap = t.kap_in;
+    ca.count = t.count;
+    ca.hdr = p->hdr;
+    XRT_TRY(launch_canon(ca, s), "canonicalize");
+    XRT_TRY(launch_scan(t.count, p->off, p->key_space, t.scan_tmp, s), "scan");
+    SortArgs sa;
+    sa.m = p->m;
+    sa.max_key = (uint32_t)(p->key_space - 1);
+    sa.key = t.key;
+    sa.tmp = t.sort_tmp;
+    sa.xc_in = t.xc_in;
+    sa.kap_in = t.kap_in;
+    sa.xc = p->xc;
+    sa.kap = p->kap;
+    sa.idx = p->idx;
+    XRT_TRY(launch_radix_sort(sa, s), "sort");
+    XRT_TRY(launch_header(p->hdr, p->off, per_v, per_v + per_h, s), "header");
+#undef XRT_TRY
+    return e;
+}
+
+xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream, bool own_buffers,
+                       xrt_plan** out)
+{
+    if (!out) return XRT_EINVAL;
+    *out = nullptr;
+    xrt_status st = plan_check(g, degree, lines);
+    if (st != XRT_OK) return st;
+
+    hipStream_t s = (hipStream_t)stream;
+    xrt_plan* p = new (std::nothrow) xrt_plan;
+    if (!p) return XRT_ENOMEM;
+    // test hook: XRT_SCHEDULE=plain selects the schedules otherwise kept
+    // for very large problems (one forward launch per strip, unsplit
+    // adjoint tiles), so that tests can compare them with the defaults
+    const char* sched = getenv("XRT_SCHEDULE");
+    const bool plain = sched && strcmp(sched, "plain") == 0;
+    plan_init(p, g, degree, lines->n, own_buffers && !plain);
 
     const int64_t m = p->m;
     Allocs al{s};
@@ -250,11 +322,6 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     // running sum per line.  Plans inside a batch need neither (the batch
     // has its own forward and adjoint launches).
     {
-        // test hook: XRT_SCHEDULE=plain selects the schedules otherwise kept
-        // for very large problems (one forward launch per strip, unsplit
-        // adjoint tiles), so that tests can compare them with the defaults
-        const char* sched = getenv("XRT_SCHEDULE");
-        const bool plain = sched && strcmp(sched, "plain") == 0;
         const int ns = std::max(p->strips_v, p->strips_h);
         const size_t sums = (size_t)ns * (size_t)m * sizeof(float);
         p->fwd_persist = own_buffers && !plain && sums <= kMaxStripSums ? 1 : 0;
@@ -272,27 +339,20 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
         } else if (own_buffers) {
             p->part = al.get<double>((size_t)m);
         }
-        // split each adjoint tile's candidate lines over up to 8 workgroups
-        // (partial images, summed in a fixed order), aiming at kAdjUnits
-        // workgroups per pass: with few units per compute unit the tiles that
-        // finish last leave it partly idle (2048^2: 2048 tiles per pass, cubic
-        // adjoint 27.9 ms unsplit, 25.4 ms split 6 ways)
-        const int64_t tiles = (int64_t)((g.nx + kTileI - 1) / kTileI) * ((g.ny + kTileJ - 1) / kTileJ);
-        p->adj_split = own_buffers && !plain ? (int)std::min<int64_t>(8, (kAdjUnits + tiles - 1) / tiles) : 1;
         p->adj_part = p->adj_split > 1 ? al.get<float>((size_t)p->adj_split * g.nx * g.ny) : nullptr;
     }
     // temporaries
-    uint32_t* key = al.get<uint32_t>(m);
-    double* xc_in = al.get<double>(m);
-    double* kap_in = al.get<double>(m);
-    uint32_t* count = al.get<uint32_t>(p->key_space);
-    const int64_t scan_words = scan_tmp_words(p->key_space);
-    uint32_t* scan_tmp = al.get<uint32_t>(scan_words);
-    uint32_t* sort_tmp = al.get<uint32_t>(radix_tmp_words(m, p->key_space - 1));
+    PlanTemps t;
+    t.key = al.get<uint32_t>(m);
+    t.xc_in = al.get<double>(m);
+    t.kap_in = al.get<double>(m);
+    t.count = al.get<uint32_t>(p->key_space);
+    t.scan_tmp = al.get<uint32_t>(scan_tmp_words(p->key_space));
+    t.sort_tmp = al.get<uint32_t>(radix_tmp_words(m, p->key_space - 1));
     auto free_tmp = [&]() {
-        void* t[] = {key, xc_in, kap_in, count, scan_tmp, sort_tmp};
-        for (void* q : t)
-            if (q) (void)hipFreeAsync(q, s);
+        void* q[] = {t.key, t.xc_in, t.kap_in, t.count, t.scan_tmp, t.sort_tmp};
+        for (void* v : q)
+            if (v) (void)hipFreeAsync(v, s);
     };
     if (al.failed) {
         set_error("hipMallocAsync", al.err);
@@ -303,58 +363,23 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
         return XRT_ENOMEM;
     }
 
-    hipError_t e = hipSuccess;
     const char* what = "plan";
     int ntab = 0;
     const float* tab = etable_host(geom_degree(degree), &ntab);
-#define XRT_TRY(call, label)                 \
-    do {                                     \
-        if (e == hipSuccess) {               \
-            e = (call);                      \
-            if (e != hipSuccess) what = label; \
-        }                                    \
-    } while (0)
-    XRT_TRY(hipMemcpyAsync(p->tab, tab, sizeof(float) * 4 * ntab, hipMemcpyHostToDevice, s),
-            "table upload");
-    XRT_TRY(hipMemsetAsync(count, 0, sizeof(uint32_t) * p->key_space, s), "memset");
-    XRT_TRY(hipMemsetAsync(p->hdr, 0, sizeof(PlanHeader), s), "memset");
-    CanonArgs ca;
-    ca.L.kind = lines->kind;
-    ca.L.theta = lines->theta;
-    ca.L.y = lines->y;
-    ca.L.ep = lines->endpoints;
-    ca.m = m;
-    ca.g = p->g;
-    ca.degree = geom_degree(degree);
-    ca.nbk_v = p->nbk_v;
-    ca.nbk_h = p->nbk_h;
-    ca.boff_v = p->boff_v;
-    ca.boff_h = p->boff_h;
-    ca.key = key;
-    ca.xc = xc_in;
-    ca.kap = kap_in;
-    ca.count = count;
-    ca.hdr = p->hdr;
-    XRT_TRY(launch_canon(ca, s), "canonicalize");
-    XRT_TRY(launch_scan(count, p->off, p->key_space, scan_tmp, s), "scan");
-    SortArgs sa;
-    sa.m = m;
-    sa.max_key = (uint32_t)(p->key_space - 1);
-    sa.key = key;
-    sa.tmp = sort_tmp;
-    sa.xc_in = xc_in;
-    sa.kap_in = kap_in;
-    sa.xc = p->xc;
-    sa.kap = p->kap;
-    sa.idx = p->idx;
-    XRT_TRY(launch_radix_sort(sa, s), "sort");
-    XRT_TRY(launch_header(p->hdr, p->off, per_v, per_v + per_h, s), "header");
+    hipError_t e = hipMemcpyAsync(p->tab, tab, sizeof(float) * 4 * ntab, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) what = "table upload";
+    if (e == hipSuccess) e = plan_build(p, lines, t, s, &what);
     PlanHeader h;
     memset(&h, 0, sizeof(h));
-    XRT_TRY(hipMemcpyAsync(&h, p->hdr, sizeof(h), hipMemcpyDeviceToHost, s), "header read");
+    if (e == hipSuccess) {
+        e = hipMemcpyAsync(&h, p->hdr, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) what = "header read";
+    }
     free_tmp();
-    XRT_TRY(hipStreamSynchronize(s), "synchronize");
-#undef XRT_TRY
+    if (e == hipSuccess) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) what = "synchronize";
+    }
     if (e != hipSuccess) {
         set_error(what, e);
         free_plan_memory(p, s);

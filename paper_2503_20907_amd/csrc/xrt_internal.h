@@ -112,6 +112,26 @@ hipError_t launch_adjoint(const xrt_plan* p, const float* sino, float* out, hipS
 hipError_t launch_adj_nonfinite(const xrt_plan* p, const float* sw, float* out, hipStream_t s);
 hipError_t launch_nnz(const xrt_plan* p, unsigned long long* out, hipStream_t s);
 
+// Temporaries of a plan build (device memory, released after it).
+struct PlanTemps {
+    uint32_t* key;       // [m]
+    double* xc_in;       // [m]
+    double* kap_in;      // [m]
+    uint32_t* count;     // [key_space]
+    uint32_t* scan_tmp;  // scan_tmp_words(key_space)
+    uint32_t* sort_tmp;  // radix_tmp_words(m, key_space - 1)
+};
+// argument checks of a plan (or plan-less call)
+xrt_status plan_check(xrt_grid g, int degree, const xrt_lines* lines);
+// sizes, bucket layout and tile split of a plan of m lines (no memory)
+void plan_init(xrt_plan* p, xrt_grid g, int degree, int64_t m, bool split_tiles);
+// enqueues the build of a plan whose buffers (xc, kap, idx, off, hdr) are
+// set: clears, canonicalisation, key counts and offsets, stable sort,
+// header.  Does not synchronise; *what names the failing step.
+hipError_t plan_build(const xrt_plan* p, const xrt_lines* lines, const PlanTemps& t, hipStream_t s,
+                      const char** what);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+
 // xrt_plan_create; own_buffers = false leaves out the buffers that only the
 // plan's own forward and adjoint use (persistent forward sums, split-tile
 // partial images): plans inside a batch, which has its own launches

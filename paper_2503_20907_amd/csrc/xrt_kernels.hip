@@ -43,6 +43,7 @@
 // with its own row arithmetic (box_row, box_F): a telescoped row sum over two
 // or four columns instead of taps and knots.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <float.h>
 #include <math.h>
 #include <stdint.h>
@@ -1722,6 +1723,19 @@ hipError_t launch_radix_sort(const SortArgs& a, hipStream_t s)
     }
     dim3 grid((unsigned)((a.m + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(k_rs_gather, grid, dim3(kBlock), 0, s, vin, a.xc_in, a.kap_in, a.xc, a.kap, a.idx, a.m);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, n, v);
     return hipGetLastError();
 }
 
