@@ -82,6 +82,41 @@ def measured_traffic(kernel: str):
     return total if found else None
 
 
+def valu_calibration(dev, iters: int = 2048, blocks_per_cu: int = 8):
+    """Issue rate of the VALU measured on xrt_calib_valu: 64 * iters
+    instructions per wave (FP32 FMA, INT32 add, FP64 FMA), 4 waves per
+    workgroup, blocks_per_cu workgroups per compute unit.  Rate = wave
+    instructions / (time x SIMDs x 2.4 GHz), i.e. instructions per cycle per
+    SIMD at the published peak clock."""
+    import torch
+
+    from paper_2503_20907_amd import _lib as L
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks = cus * blocks_per_cu
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    res = {"cus": cus, "simds": 4 * cus, "blocks": blocks, "iters": iters,
+           "valu_per_wave": 64 * iters, "clock_ghz_assumed": 2.4}
+    for mode, name in ((0, "fma_f32"), (1, "add_u32"), (2, "fma_f64")):
+        for _ in range(2):
+            assert L.xrt_calib_valu(mode, iters, blocks, out.data_ptr(), stream.cuda_stream) == 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 5
+        for _ in range(reps):
+            L.xrt_calib_valu(mode, iters, blocks, out.data_ptr(), stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        wave_instr = blocks * 4 * 64 * iters
+        rate = wave_instr / (t * 4 * cus * 2.4e9)
+        res[name] = {"ms": round(t * 1e3, 4), "wave_instructions": wave_instr,
+                     "instr_per_cycle_per_simd": round(rate, 4)}
+        print(f"[bench] valu calibration {name}: {t * 1e3:.3f} ms, {rate:.4f} wave instructions "
+              f"per cycle per SIMD at 2.4 GHz", file=sys.stderr, flush=True)
+    return res
+
+
 def flops_per_nonzero(n: int) -> int:
     # one degree-(2n+1) polynomial evaluation (2n+1 FMAs) + one FMA, 2 flops each
     return 4 * n + 4
@@ -282,6 +317,8 @@ def main():
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
+    ap.add_argument("--valu-calib", action="store_true",
+                    help="only run the VALU calibration kernel (known instruction count) and print its issue rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -309,6 +346,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_mib": args.copy_only, "bytes_read": nel * 4,
                           "bytes_written": nel * 4}), flush=True)
+        return
+    if args.valu_calib:
+        print(json.dumps(valu_calibration(dev)), flush=True)
         return
     N, n = args.grid, args.degree
     print(f"[bench] building workload {N}^2 degree {n}", file=sys.stderr, flush=True)

@@ -44,6 +44,8 @@ EXPORTS = (
     "xrt_batch_create", "xrt_batch_destroy", "xrt_batch_buffers", "xrt_batch_info", "xrt_batch_forward",
     "xrt_batch_adjoint", "xrt_batch_run", "xrt_batch_get_config", "xrt_batch_set_config",
     "xrt_batch_autotune",
+    # xrt_bench.h
+    "xrt_calib_valu",
 )
 
 
@@ -107,6 +109,8 @@ def load() -> ctypes.CDLL:
     lib.xrt_forward.argtypes = [vp, XrtGrid, i32, ctypes.POINTER(XrtLines), vp, vp]
     lib.xrt_adjoint.argtypes = [vp, ctypes.POINTER(XrtLines), i32, XrtGrid, vp, vp]
     lib.xrt_adjoint_noalloc.argtypes = [vp, ctypes.POINTER(XrtLines), i32, XrtGrid, vp, vp]
+    lib.xrt_calib_valu.argtypes = [i32, i32, i32, vp, vp]
+    lib.xrt_calib_valu.restype = i32
     lib.xrt_plan_create.argtypes = [XrtGrid, i32, ctypes.POINTER(XrtLines), vp,
                                     ctypes.POINTER(vp)]
     lib.xrt_plan_forward.argtypes = [vp, vp, vp, vp]
@@ -198,6 +202,10 @@ def xrt_adjoint(sino, lines: XrtLines, degree: int, grid: XrtGrid, coeffs_out, s
 
 def xrt_adjoint_noalloc(sino, lines: XrtLines, degree: int, grid: XrtGrid, coeffs_out, stream) -> int:
     return load().xrt_adjoint_noalloc(sino, ctypes.byref(lines), int(degree), grid, coeffs_out, stream)
+
+
+def xrt_calib_valu(mode: int, iters: int, blocks: int, out, stream) -> int:
+    return load().xrt_calib_valu(int(mode), int(iters), int(blocks), out, stream)
 
 
 def xrt_plan_create(grid: XrtGrid, degree: int, lines: XrtLines, stream):

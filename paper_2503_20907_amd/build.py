@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxrt.so")
 SOURCES = ["xrt_kernels.hip", "xrt_api.cpp", "xrt_learn.hip", "xrt_learn.cpp", "xrt_batch.cpp",
-           "xrt_noalloc.hip"]
+           "xrt_noalloc.hip", "xrt_calib.hip"]
 ARCH = os.environ.get("XRT_OFFLOAD_ARCH", "gfx950")
 
 

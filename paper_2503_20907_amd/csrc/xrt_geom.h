@@ -169,17 +169,74 @@ XRT_HD inline uint32_t mul24(uint32_t a, uint32_t b)
 #endif
 }
 
-// First knot slot of a row relative to its first tap J - n, for S slots:
-// the S knots nearest to q = X + (n+1)/2, centred on round(q) for odd S
-// (t = fraction of q) and on q for even S.
-template <int N, int S>
-XRT_HD inline int adj_knot_offset(float t)
+// Offset o of the first of the S knot slots of a row from J = floor(q),
+// q = X + (n+1)/2: the S knots nearest to q, centred on round(q) for odd S
+// (up: the fraction of q is at least 1/2) and on q for even S.
+template <int S>
+XRT_HD inline int knot_o(bool up)
 {
     if constexpr (S % 2 == 0) {
-        return 1 - S / 2 + N;
+        return 1 - S / 2;
     } else {
-        return (t >= 0.5f ? 1 : 0) - (S - 1) / 2 + N;
+        return (up ? 1 : 0) - (S - 1) / 2;
     }
+}
+
+// First knot slot of a row relative to its first tap J - n.
+template <int N, int S>
+XRT_HD inline int adj_knot_offset(bool up)
+{
+    return knot_o<S>(up) + N;
+}
+
+// The adjoint walks a line's rows in 32.32 fixed point: Q(jj) = Q0 + jj Kq
+// with Q0 = round((q - n) 2^32) at the line's first row in the tile and
+// Kq = round(kappa 2^32), so that floor(q - n) (the first tap's column) is
+// the high word and the fraction the low word.  Consecutive rows differ by
+// one 32-bit add with carry into the accumulator address; the rounding of
+// Q0 and Kq moves a row's position by at most (1 + jj) 2^-33 cells.
+struct AdjFix {
+    int64_t Q0;    // fixed-point q - n at tile row row0 (jj = 0)
+    int64_t Kq;    // fixed-point slope
+    uint32_t Kf;   // low word of Kq (fraction step)
+    uint32_t Wk;   // W + high word of Kq: address step before the carry
+    int row0, W;
+};
+
+XRT_HD inline AdjFix adj_fix(double qn, double kap, int row0, int W)
+{
+    AdjFix f;
+    f.Q0 = (int64_t)rint(qn * 4294967296.0);
+    f.Kq = (int64_t)rint(kap * 4294967296.0);
+    f.Kf = (uint32_t)f.Kq;
+    f.Wk = (uint32_t)W + (uint32_t)(int32_t)(f.Kq >> 32);
+    f.row0 = row0;
+    f.W = W;
+    return f;
+}
+
+// Row jj of the walk: its fraction (low word) and the accumulator word of its
+// first tap, row (row0 + jj) times the pitch W plus floor(q - n).
+struct AdjStep {
+    uint32_t tf;
+    uint32_t base;
+};
+
+XRT_HD inline AdjStep adj_fix_at(const AdjFix& f, int jj)
+{
+    const int64_t Q = f.Q0 + (int64_t)jj * f.Kq;
+    AdjStep st;
+    st.tf = (uint32_t)Q;
+    st.base = mul24((uint32_t)(f.row0 + jj), (uint32_t)f.W) + (uint32_t)(int32_t)(Q >> 32);
+    return st;
+}
+
+// Row jj -> jj + 1 (exact: equals adj_fix_at(f, jj + 1)).
+XRT_HD inline void adj_fix_next(const AdjFix& f, AdjStep& st)
+{
+    const uint32_t tn = st.tf + f.Kf;
+    st.base += f.Wk + (tn < st.tf ? 1u : 0u);
+    st.tf = tn;
 }
 
 // Accumulator word of a row's first tap: row (within the tile) times the

@@ -430,6 +430,30 @@ struct TabRef {
     const GTab* mem;
 };
 
+// The S knot values of a row at fraction t (up: t >= 1/2), not yet
+// multiplied by r^n: z_s = (q - K0 - s)/r with K0 = J + knot_o(up).
+template <int N, int S, int G = 0>
+__device__ inline void row_knots(float t, bool up, const LineConst& k, TabRef tab, float* g)
+{
+    const int o = knot_o<S>(up);
+    // o / r in table units (loop-invariant choices)
+    float oz;
+    if constexpr (S % 2 == 1) {
+        oz = up ? (float)(1 - (S - 1) / 2) * k.inv_tab : (float)(-((S - 1) / 2)) * k.inv_tab;
+    } else {
+        oz = (float)o * k.inv_tab;
+    }
+    // z_s = (q - K0 - s) / r, in table units; knot K0 + s lies at or left of
+    // q (z_s >= 0) exactly when o + s <= 0
+    const float a0 = fmaf(t, k.inv_tab, -oz);
+    g[0] = G > 0 ? etab<N>(tab.mem, a0, o <= 0) : etab<N>(tab.lds, a0, o <= 0);
+#pragma unroll
+    for (int sl = 1; sl < S; ++sl) {
+        const float z = fmaf(-(float)sl, k.inv_tab, a0);
+        g[sl] = sl < G ? etab<N>(tab.mem, z, o + sl <= 0) : etab<N>(tab.lds, z, o + sl <= 0);
+    }
+}
+
 template <int N, int S, int G = 0>
 __device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>& R)
 {
@@ -438,27 +462,9 @@ __device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>
     const float t = (float)frac_pos(q);
     R.J = (int)q;
     R.t = t;
-    // the S knots nearest to q: centred on round(q) for odd S, on q for even S
-    int o;
-    float oz;  // o / r in table units (loop-invariant choices)
-    if constexpr (S % 2 == 1) {
-        const bool up = t >= 0.5f;
-        o = (up ? 1 : 0) - (S - 1) / 2;
-        oz = up ? (float)(1 - (S - 1) / 2) * k.inv_tab : (float)(-((S - 1) / 2)) * k.inv_tab;
-    } else {
-        o = 1 - S / 2;
-        oz = (float)o * k.inv_tab;
-    }
-    R.K0 = R.J + o;
-    // z_s = (q - K0 - s) / r, in table units; knot K0 + s lies at or left of
-    // q (z_s >= 0) exactly when o + s <= 0
-    const float a0 = fmaf(t, k.inv_tab, -oz);
-    R.g[0] = G > 0 ? etab<N>(tab.mem, a0, o <= 0) : etab<N>(tab.lds, a0, o <= 0);
-#pragma unroll
-    for (int sl = 1; sl < S; ++sl) {
-        const float z = fmaf(-(float)sl, k.inv_tab, a0);
-        R.g[sl] = sl < G ? etab<N>(tab.mem, z, o + sl <= 0) : etab<N>(tab.lds, z, o + sl <= 0);
-    }
+    const bool up = t >= 0.5f;
+    R.K0 = R.J + knot_o<S>(up);
+    row_knots<N, S, G>(t, up, k, tab, R.g);
 }
 
 // sum_d w_d(t) c_{J-d} written in powers of t, times kTapScale<N> (c[0] is
@@ -639,20 +645,31 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     uint32_t off = (uint32_t)ja * (uint32_t)pitch * 4u;
     const uint32_t step = (uint32_t)pitch * 4u;
     float part = 0.f;
-    // walk q - N (exact): its floor is the first tap J - N, so that the taps
-    // and the knot slots (at J - N + N + o) share one offset register
-    q -= (double)N;
+    // walk q - N: its floor is the first tap J - N, so that the taps and the
+    // knot slots (at J - N + N + o) share one offset register.  The walk is
+    // in 32.32 fixed point, as the adjoint's (adj_fix): the fraction in the
+    // low word, the column in the high word, one add with carry per row.
+    const int64_t Q0 = (int64_t)rint((q - (double)N) * 4294967296.0);
+    const int64_t Kq = (int64_t)rint(kap * 4294967296.0);
+    const uint32_t Kf = (uint32_t)Kq;
+    const int Ki = (int)(Kq >> 32);
+    uint32_t tf = (uint32_t)Q0;
+    int J = (int)(Q0 >> 32);
     for (int j = ja; j <= jb; ++j) {
-        Row<S> R;
-        row_core<N, S>(q, lc, TabRef{tab, nullptr}, R);
+        const float t = (float)tf * 0x1p-32f;
+        const bool up = t >= 0.5f;
+        float g[S];
+        row_knots<N, S>(t, up, lc, TabRef{tab, nullptr}, g);
         float cv[N + 1], dv[S];
-        load_run<N + 1>((const float*)(Cb + (off + (uint32_t)R.J * 4u)), cv);
-        load_run<S>((const float*)(Db + (off + (uint32_t)(R.K0 + N) * 4u)), dv);
-        float es = R.g[0] * dv[0];
+        load_run<N + 1>((const float*)(Cb + (off + (uint32_t)J * 4u)), cv);
+        load_run<S>((const float*)(Db + (off + (uint32_t)(J + knot_o<S>(up) + N) * 4u)), dv);
+        float es = g[0] * dv[0];
 #pragma unroll
-        for (int sl = 1; sl < S; ++sl) es = fmaf(R.g[sl], dv[sl], es);
-        part += fmaf(ern, es, tap_sum<N>(R.t, rho, cv));
-        q += kap;
+        for (int sl = 1; sl < S; ++sl) es = fmaf(g[sl], dv[sl], es);
+        part += fmaf(ern, es, tap_sum<N>(t, rho, cv));
+        const uint32_t tn = tf + Kf;
+        J += Ki + (tn < tf ? 1 : 0);
+        tf = tn;
         off += step;
     }
     return part;
@@ -665,14 +682,20 @@ template <bool NEG>
 __device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const BoxRow& bk,
                                      const float* __restrict__ C, int pitch)
 {
-    // q = X + kPad at row ja (padded column coordinate, positive)
+    // q = X + kPad at row ja (padded column coordinate, positive); walked in
+    // 32.32 fixed point (fraction in the low word, column in the high word)
     const char* __restrict__ Cb = (const char*)C;
     uint32_t off = (uint32_t)ja * (uint32_t)pitch * 4u;
     const uint32_t step = (uint32_t)pitch * 4u;
     float part = 0.f;
+    const int64_t Q0 = (int64_t)rint(q * 4294967296.0);
+    const int64_t Kq = (int64_t)rint(kap * 4294967296.0);
+    const uint32_t Kf = (uint32_t)Kq;
+    const uint32_t Ki = (uint32_t)(int32_t)(Kq >> 32);
+    uint32_t tf = (uint32_t)Q0;
+    uint32_t i0 = (uint32_t)(int32_t)(Q0 >> 32);
     for (int j = ja; j <= jb; ++j) {
-        const float t = (float)__builtin_amdgcn_fract(q);
-        const uint32_t i0 = (uint32_t)(int)q;
+        const float t = (float)tf * 0x1p-32f;
         if constexpr (NEG) {
             float c[4];
             load_run<4>((const float*)(Cb + (off + (i0 - 1u) * 4u)), c);
@@ -684,7 +707,9 @@ __device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const
             load_run<2>((const float*)(Cb + (off + i0 * 4u)), c);
             part += fmaf(box_F1(t, bk), c[1] - c[0], c[0]);
         }
-        q += kap;
+        const uint32_t tn = tf + Kf;
+        i0 += Ki + (tn < tf ? 1u : 0u);
+        tf = tn;
         off += step;
     }
     return part;
@@ -1033,6 +1058,54 @@ __device__ constexpr int adj_mem_slots()
 }
 
 template <int N, int S, bool L1>
+__device__ inline void adj_row(AdjStep st, float svkr, const TapScaled<N>& tk, const LineConst& lc, TabRef s_tab,
+                               int* s_a, int* s_k)
+{
+    // (float) of the low word rounds to nearest and can give t = 1.0 just
+    // below a knot: the taps then take the left cell's polynomial at its right
+    // end and the knots their integer side (row_knots), which agree
+    const float t = (float)st.tf * 0x1p-32f;
+    const bool up = t >= 0.5f;
+    // the knot slots' table entries are fetched first (as row_knots forms
+    // them), so that their latency overlaps the tap weights and the tap
+    // atomics (2048^2 cubic adjoint 24.8 -> 24.2 ms)
+    constexpr int G = adj_mem_slots<N, S, L1>();
+    constexpr int last = kTabPerUnit * (N + 1) / 2;
+    const int o = knot_o<S>(up);
+    float oz;
+    if constexpr (S % 2 == 1) {
+        oz = up ? (float)(1 - (S - 1) / 2) * lc.inv_tab : (float)(-((S - 1) / 2)) * lc.inv_tab;
+    } else {
+        oz = (float)o * lc.inv_tab;
+    }
+    const float a0 = fmaf(t, lc.inv_tab, -oz);
+    f4v cf[S];
+    float tau[S];
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+        const float z = sl == 0 ? a0 : fmaf(-(float)sl, lc.inv_tab, a0);
+        const float a = fminf(fabsf(z), (float)last);
+        const int i = (int)a;
+        tau[sl] = __builtin_amdgcn_fractf(a);
+        cf[sl] = sl < G ? tab_at(s_tab.mem, (uint32_t)i << 4) : tab_at(s_tab.lds, (uint32_t)i << 4);
+    }
+    int wi[N + 1];
+    tap_fixed<N>(t, tk, wi);
+    int* ar = s_a + st.base;  // taps J-N .. J, ascending
+    int* kr = s_k + st.base + (uint32_t)adj_knot_offset<N, S>(up);
+#pragma unroll
+    for (int d = 0; d <= N; ++d) atomicAdd(ar + d, wi[N - d]);
+#pragma unroll
+    for (int sl = 0; sl < S; ++sl) {
+        // E at the slot (etab's Horner and parity; o + sl <= 0: knot at or
+        // left of q)
+        float g = fmaf(tau[sl], fmaf(tau[sl], fmaf(tau[sl], cf[sl].w, cf[sl].z), cf[sl].y), cf[sl].x);
+        if constexpr (N % 2 == 0) g = (o + sl <= 0) ? -g : g;
+        atomicAdd(kr + sl, fixed_round(svkr, g));
+    }
+}
+
+template <int N, int S, bool L1>
 __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float svs, float svk,
                                 const LineConst& lc, int W, TabRef s_tab,
                                 int* s_a, int* s_k)
@@ -1042,31 +1115,25 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     // LDS word in one instruction.  The lane index is scrambled (37 l mod 64):
     // neighbouring lanes hold neighbouring lines, and giving them neighbouring
     // rows (l cnt / 64) took 33 ms instead of 25 (2048^2 cubic adjoint).
-    int jj = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
+    const int jj0 = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
     const float svkr = svk * lc.rn;
     const TapScaled<N> tk = tap_scaled<N>(svs, lc.rho);
-    // knot slots start at K0 = J + o (o = 1 - S/2 for even S, a constant),
-    // so that taps and slots share one base address at J - N
     // walk q - N (exact): its floor is the first tap J - N (at least 0: the
-    // halo covers the footprint), which is the base address of the row
-    const double q0n = q0 - (double)N;
-    // every row once, from jj round to jj (cnt >= 1)
-    const int jstart = jj;
+    // halo covers the footprint), which is the base address of the row; the
+    // knot slots share it (at J + o, adj_knot_offset).  Rows jj0 .. cnt-1,
+    // then (back to row 0) 0 .. jj0-1, in one loop: every lane of a wave then
+    // takes cnt steps (two loops would take up to twice as many, since the
+    // lanes' start rows are spread).  The address grows by at least W - 1
+    // per row, so it marks the wrap and the end.
+    const AdjFix F = adj_fix(q0 - (double)N, kap, row0, W);
+    AdjStep st = adj_fix_at(F, jj0);
+    const AdjStep st0 = adj_fix_at(F, 0);
+    const uint32_t mid = st.base, end = adj_fix_at(F, cnt).base;
     do {
-        const double q = fma(kap, (double)jj, q0n);
-        Row<S> R;
-        row_core<N, S, adj_mem_slots<N, S, L1>()>(q, lc, s_tab, R);
-        int wi[N + 1];
-        tap_fixed<N>(R.t, tk, wi);
-        const uint32_t base = adj_tap_base(row0 + jj, W, R.J);
-        int* ar = s_a + base;  // taps J-N .. J, ascending
-        int* kr = s_k + base + (uint32_t)adj_knot_offset<N, S>(R.t);
-#pragma unroll
-        for (int d = 0; d <= N; ++d) atomicAdd(ar + d, wi[N - d]);
-#pragma unroll
-        for (int sl = 0; sl < S; ++sl) atomicAdd(kr + sl, fixed_round(svkr, R.g[sl]));
-        if (++jj == cnt) jj = 0;
-    } while (jj != jstart);
+        adj_row<N, S, L1>(st, svkr, tk, lc, s_tab, s_a, s_k);
+        adj_fix_next(F, st);
+        if (st.base == end) st = st0;
+    } while (st.base != mid);
 }
 
 // Box spline: the row weights psi(X - i) = F_{i-i0} - F_{i-i0+1} of the
@@ -1076,16 +1143,17 @@ template <bool NEG>
 __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, float svs, const BoxRow& bk,
                                     int W, int* s_a)
 {
-    // start row spread as in adj_walk
-    int jj = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
-    // every row once, from jj round to jj (cnt >= 1)
-    const int jstart = jj;
+    // start row spread and fixed-point walk as in adj_walk, on q - 1: its
+    // floor is the first column floor(q) - 1 (columns floor(q) - 1 ..
+    // floor(q) + 2)
+    const int jj0 = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
+    const AdjFix F = adj_fix(q0 - 1.0, kap, row0, W);
+    AdjStep st = adj_fix_at(F, jj0);
+    const AdjStep st0 = adj_fix_at(F, 0);
+    const uint32_t mid = st.base, end = adj_fix_at(F, cnt).base;
     do {
-        // q > 0 (halo-relative column), so truncation is the floor
-        const double q = fma(kap, (double)jj, q0);
-        const float t = (float)__builtin_amdgcn_fract(q);
-        // columns floor(q) - 1 .. floor(q) + 2
-        int* ar = s_a + adj_tap_base(row0 + jj, W, (int)q - 1);
+        const float t = (float)st.tf * 0x1p-32f;
+        int* ar = s_a + st.base;
         if constexpr (NEG) {
             // kappa < 0: 1 - F_0 = k0 p^2 is formed directly
             const float p = fmaxf(bk.a - t, 0.f), qq = fmaxf(t + bk.am1, 0.f);
@@ -1100,20 +1168,20 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
             atomicAdd(ar + 1, fixed_round(svs, 1.f - F));
             atomicAdd(ar + 2, fixed_round(svs, F));
         }
-        if (++jj == cnt) jj = 0;
-    } while (jj != jstart);
+        adj_fix_next(F, st);
+        if (st.base == end) st = st0;
+    } while (st.base != mid);
 }
 
-__device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, float sv, int e, bool vert, int maj0,
-                                    int min0, int TM, int TN, int nmaj, int W, double jc, double marg, int* s_a)
+__device__ inline void adj_line_box(const AdjArgs& A, double xck, double kap, bool active, float sv, int e, bool vert,
+                                    int maj0, int min0, int TM, int TN, int nmaj, int W, double jc, double marg, int* s_a)
 {
     if (!active) return;
-    const double kap = A.kap[k];
     const int nmin = vert ? A.nx : A.ny;
     // rows whose crossing lies within the footprint's half-width (1 for
     // kappa >= 0, 1 + |kappa| otherwise; at most marg) of the tile
     const double ml = kap >= 0.0 ? 1.0 : 1.0 - kap;
-    const AdjRows rr = adj_rows(A.xc[k], kap, jc, ml, nmaj, nmin, maj0, min0, TM, TN);
+    const AdjRows rr = adj_rows(xck, kap, jc, ml, nmaj, nmin, maj0, min0, TM, TN);
     const int ra = rr.ra, rb = rr.rb;
     const double x0 = rr.x0;
     (void)marg;
@@ -1125,7 +1193,7 @@ __device__ inline void adj_line_box(const AdjArgs& A, uint32_t k, bool active, f
 }
 
 template <int N, bool L1>
-__device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float sv, int e,
+__device__ inline void adj_line(const AdjArgs& A, double xck, double kapk, bool active, float sv, int e,
                                 bool vert, int maj0, int min0, int TM, int TN, int nmaj, int W,
                                 double jc, double marg, TabRef s_tab, int* s_a,
                                 int* s_k)
@@ -1134,11 +1202,11 @@ __device__ inline void adj_line(const AdjArgs& A, uint32_t k, bool active, float
     int ra = 0, rb = -1;
     double kap = 0.0, x0 = 0.0;
     if (active) {
-        kap = A.kap[k];
+        kap = kapk;
         const int nmin = vert ? A.nx : A.ny;
         // rows whose crossing lies within the footprint's half-width
         // H (1 + |kappa|) of the tile (at most marg)
-        const AdjRows rr = adj_rows(A.xc[k], kap, jc, H * (1.0 + fabs(kap)), nmaj, nmin, maj0, min0, TM, TN);
+        const AdjRows rr = adj_rows(xck, kap, jc, H * (1.0 + fabs(kap)), nmaj, nmin, maj0, min0, TM, TN);
         ra = rr.ra;
         rb = rr.rb;
         x0 = rr.x0;
@@ -1305,11 +1373,14 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
             __syncthreads();
             uint32_t kk[kAdjLpt];
             float svv[kAdjLpt];
+            double xcv[kAdjLpt], kpv[kAdjLpt];
             float amax = 0.f;
 #pragma unroll
             for (int u = 0; u < kAdjLpt; ++u) {
                 kk[u] = 0;
                 svv[u] = 0.f;
+                xcv[u] = 0.0;
+                kpv[u] = 0.0;
                 const uint32_t item = base + (uint32_t)(u * kBlock + tid);
                 if (item < total) {
                     const int r = (u << 3) | ((tid >> 6) << 1);
@@ -1321,6 +1392,10 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                     }
                     kk[u] = s_start[lo] + (item - s_pre[lo]);
                     svv[u] = A.sw[kk[u]];
+                    // the line records are loaded with the value (one
+                    // latency instead of two before the walk)
+                    xcv[u] = A.xc[kk[u]];
+                    kpv[u] = A.kap[kk[u]];
                 }
                 // a NaN or infinite value is left out here (it would break
                 // the chunk's scale); k_adj_nonfinite marks its pixels
@@ -1337,10 +1412,10 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
 #pragma unroll
             for (int u = 0; u < kAdjLpt; ++u) {
                 if constexpr (N == kBox3)
-                    adj_line_box(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg,
+                    adj_line_box(A, xcv[u], kpv[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg,
                                  s_a);
                 else
-                    adj_line<N, L1>(A, kk[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
+                    adj_line<N, L1>(A, xcv[u], kpv[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
                                 jc, marg, s_tab, s_a, s_k);
             }
             __syncthreads();

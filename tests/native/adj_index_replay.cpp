@@ -2,10 +2,12 @@
 //
 // For random lines on several grids, every (pixel tile, line) pair of both
 // adjoint passes goes through the same functions the kernels use
-// (canon_core, adj_rows, adj_q0, adj_tap_base, adj_knot_offset, from
-// xrt_geom.h), and every accumulator word a row would update is checked to
-// lie inside its own accumulator row: taps and knot slots in [0, W) of row
-// (row0 + jj), rows in [0, TM).  Built with AddressSanitizer and
+// (canon_core, adj_rows, adj_q0, the fixed-point walk adj_fix / adj_fix_at /
+// adj_fix_next, adj_tap_base, adj_knot_offset, from xrt_geom.h), and every
+// accumulator word a row would update is checked to lie inside its own
+// accumulator row: taps and knot slots in [0, W) of row (row0 + jj), rows in
+// [0, TM).  The walk must visit every row once, wrap and end on the
+// addresses it tests for, and each step must equal the direct evaluation.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer (float-to-int overflow included) by
 // tests/test_sanitizers.py.  Exit status 0: every address in bounds.
 #include <math.h>
@@ -36,26 +38,45 @@ static void walk_bspline(double xc, double kap, const AdjRows& rr, int maj0, int
 {
     const double H = 0.5 * (N + 1);
     const double q0 = adj_q0(rr.x0, kap, rr.ra, min0, H);
-    const double q0n = q0 - (double)N;
     const int cnt = rr.rb - rr.ra + 1, row0 = rr.ra - maj0;
-    for (int jj = 0; jj < cnt; ++jj) {
-        const double q = fma(kap, (double)jj, q0n);
-        const int row = row0 + jj;
-        if (row < 0 || row >= TM) fail("row", N, xc, kap, maj0, min0, row, 0);
-        if (!(q > 0.0)) {
-            fail("q <= 0", N, xc, kap, maj0, min0, row, 0);
-            continue;
-        }
-        const int J = (int)q;
-        const float t = (float)frac_pos(q);
-        const uint32_t base = adj_tap_base(row, W, J);
-        const uint32_t lo = (uint32_t)row * (uint32_t)W, hi = lo + (uint32_t)W;
-        for (int d = 0; d <= N; ++d)
-            if (base + d < lo || base + d >= hi) fail("tap", N, xc, kap, maj0, min0, row, J + d);
-        const uint32_t kb = base + (uint32_t)adj_knot_offset<N, S>(t);
-        for (int sl = 0; sl < S; ++sl)
-            if (kb + sl < lo || kb + sl >= hi) fail("knot", N, xc, kap, maj0, min0, row, (int)(kb + sl - lo));
-        ++g_rows;
+    // the kernel's fixed-point walk: rows jj0 .. cnt-1, then back to row 0
+    // and on to jj0-1, for start rows jj0 of several lanes
+    const AdjFix F = adj_fix(q0 - (double)N, kap, row0, W);
+    const uint32_t end = adj_fix_at(F, cnt).base;
+    for (int lane = 0; lane < 64; lane += 7) {
+        const int jj0 = (int)((((unsigned)lane * 37u) & 63u) * (unsigned)cnt >> 6);
+        AdjStep st = adj_fix_at(F, jj0);
+        const uint32_t mid = st.base;
+        int jj = jj0, steps = 0;
+        auto visit = [&](const AdjStep& a, int j) {
+            const int row = row0 + j;
+            if (row < 0 || row >= TM) fail("row", N, xc, kap, maj0, min0, row, 0);
+            const uint32_t lo = (uint32_t)row * (uint32_t)W, hi = lo + (uint32_t)W;
+            // the step must equal the direct evaluation at this row
+            const AdjStep d = adj_fix_at(F, j);
+            if (d.base != a.base || d.tf != a.tf) fail("step", N, xc, kap, maj0, min0, row, 0);
+            const bool up = (float)a.tf * 0x1p-32f >= 0.5f;
+            for (int t = 0; t <= N; ++t)
+                if (a.base + t < lo || a.base + t >= hi) fail("tap", N, xc, kap, maj0, min0, row, (int)(a.base + t - lo));
+            const uint32_t kb = a.base + (uint32_t)adj_knot_offset<N, S>(up);
+            for (int sl = 0; sl < S; ++sl)
+                if (kb + sl < lo || kb + sl >= hi) fail("knot", N, xc, kap, maj0, min0, row, (int)(kb + sl - lo));
+            ++g_rows;
+        };
+        const AdjStep st0 = adj_fix_at(F, 0);
+        do {
+            visit(st, jj);
+            adj_fix_next(F, st);
+            ++jj;
+            if (st.base == end) {
+                if (jj != cnt) fail("wrap row", N, xc, kap, maj0, min0, jj, cnt);
+                st = st0;
+                jj = 0;
+            }
+            if (++steps > TM + 1) { fail("no end", N, xc, kap, maj0, min0, jj, 0); break; }
+        } while (st.base != mid);
+        if (steps != cnt) fail("row count", N, xc, kap, maj0, min0, steps, cnt);
+        if (jj != jj0) fail("end row", N, xc, kap, maj0, min0, jj, jj0);
     }
 }
 
@@ -85,19 +106,32 @@ static void line_tile_box(double xc, double kap, int nmaj, int nmin, int maj0, i
     if (rr.ra > rr.rb) return;
     const double q0 = adj_q0(rr.x0, kap, rr.ra, min0, 0.0);
     const int cnt = rr.rb - rr.ra + 1, row0 = rr.ra - maj0;
-    for (int jj = 0; jj < cnt; ++jj) {
-        const double q = fma(kap, (double)jj, q0);
-        const int row = row0 + jj;
-        if (row < 0 || row >= TM) fail("row", 16, xc, kap, maj0, min0, row, 0);
-        if (!(q > 1.0)) {
-            fail("q <= 1", 16, xc, kap, maj0, min0, row, 0);
-            continue;
-        }
-        const uint32_t base = adj_tap_base(row, W, (int)q - 1);
-        const uint32_t lo = (uint32_t)row * (uint32_t)W, hi = lo + (uint32_t)W;
-        for (int d = 0; d < 4; ++d)
-            if (base + d < lo || base + d >= hi) fail("box column", 16, xc, kap, maj0, min0, row, (int)(base + d - lo));
-        ++g_rows;
+    // the kernel's walk on q - 1: base = row W + floor(q) - 1
+    const AdjFix F = adj_fix(q0 - 1.0, kap, row0, W);
+    const uint32_t end = adj_fix_at(F, cnt).base;
+    for (int lane = 0; lane < 64; lane += 7) {
+        const int jj0 = (int)((((unsigned)lane * 37u) & 63u) * (unsigned)cnt >> 6);
+        AdjStep st = adj_fix_at(F, jj0);
+        const AdjStep st0 = adj_fix_at(F, 0);
+        const uint32_t mid = st.base;
+        int jj = jj0, steps = 0;
+        do {
+            const int row = row0 + jj;
+            if (row < 0 || row >= TM) fail("row", 16, xc, kap, maj0, min0, row, 0);
+            const uint32_t lo = (uint32_t)row * (uint32_t)W, hi = lo + (uint32_t)W;
+            for (int d = 0; d < 4; ++d)
+                if (st.base + d < lo || st.base + d >= hi)
+                    fail("box column", 16, xc, kap, maj0, min0, row, (int)(st.base + d - lo));
+            ++g_rows;
+            adj_fix_next(F, st);
+            ++jj;
+            if (st.base == end) {
+                st = st0;
+                jj = 0;
+            }
+            if (++steps > TM + 1) { fail("no end", 16, xc, kap, maj0, min0, jj, 0); break; }
+        } while (st.base != mid);
+        if (steps != cnt) fail("row count", 16, xc, kap, maj0, min0, steps, cnt);
     }
 }
 
