@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 
 # The sources that decide what the profiled kernels do: their code and their
 # launch configuration (tile split, grid sizes, layouts).
-KERNEL_SOURCES = ("xrt_kernels.hip", "xrt_api.cpp", "xrt_internal.h")
+KERNEL_SOURCES = ("xrt_kernels.hip", "xrt_api.cpp", "xrt_internal.h", "xrt_geom.h")
 
 
 def kernel_source_hash(paths=None) -> str:
@@ -62,10 +62,11 @@ def kernel_source_hash(paths=None) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
-    (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or None if
-    the kernel source changed since the counters were taken."""
+def measured_traffic(call: str):
+    """HBM bytes of one `call` ("adjoint" or "forward": every kernel the call
+    launches, each as often as it launches it) from the committed rocprofv3
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated against a copy kernel), or
+    None if the kernel sources changed since the counters were taken."""
     import re
     srcs = [os.path.join(ROOT, "paper_2503_20907_amd", "csrc", f) for f in KERNEL_SOURCES]
     summ = os.path.join(ROOT, "profiles", "hbm_traffic_2048_cubic_fan_random.md")
@@ -74,10 +75,11 @@ def measured_traffic(kernel: str):
     sha = kernel_source_hash(srcs)
     total = 0
     found = False
+    pat = r"traffic call=(\w+) kernel=(\S+) count=(\d+) sha=(\w+) read_bytes=(\d+) write_bytes=(\d+)"
     for line in open(summ):
-        m = re.search(r"traffic kernel=(\S+) sha=(\w+) read_bytes=(\d+) write_bytes=(\d+)", line)
-        if m and m.group(1).startswith(kernel) and m.group(2) == sha:
-            total += int(m.group(3)) + int(m.group(4))
+        m = re.search(pat, line)
+        if m and m.group(1) == call and m.group(4) == sha:
+            total += int(m.group(3)) * (int(m.group(5)) + int(m.group(6)))
             found = True
     return total if found else None
 
@@ -115,6 +117,43 @@ def valu_calibration(dev, iters: int = 2048, blocks_per_cu: int = 8):
         print(f"[bench] valu calibration {name}: {t * 1e3:.3f} ms, {rate:.4f} wave instructions "
               f"per cycle per SIMD at 2.4 GHz", file=sys.stderr, flush=True)
     return res
+
+
+def unet_timing(dev, applies: int = 10, steps: int = 5, batch: int = 4):
+    """The reconstruction workload's U-Net (512 x 512, 6 levels, 32..256
+    channels, random weights): mean time of an apply and of a residual-space
+    training step (batch 4: forward, loss through the normal operator,
+    backward, Adam), for profiling the network's kernels."""
+    import torch
+
+    import xrt_workloads as W
+    from paper_2503_20907_amd import learn, ops
+    N, lam = 512, 1e-2
+    spec, _ = W.recon_problem(N, 180, 768)
+    plan = ops.Plan(N, N, 3, ops.Lines.from_spec(spec))
+    net = learn.UNet(N, N, levels=6, base=32, max_batch=batch, seed=1, max_channels=256)
+    fields = W.training_fields(batch, N, N, seed=3, device=dev)
+    R = learn.make_pairs(plan, lam, fields)
+    net.gain = learn.typical_gain(R, fields)
+    z = torch.empty_like(R[0])
+    for _ in range(2):
+        net.apply(R[0], z)
+        net.train_step_normal(plan, lam, R, 1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(applies):
+        net.apply(R[0], z)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step_normal(plan, lam, R, 1e-5)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"apply_ms": round((t1 - t0) / applies * 1e3, 4), "train_step_ms": round((t2 - t1) / steps * 1e3, 4),
+           "batch": batch, "params": int(net.num_params)}
+    net.close()
+    plan.close()
+    return out
 
 
 def flops_per_nonzero(n: int) -> int:
@@ -158,7 +197,19 @@ def cpu_baseline(spec, coeffs, degree, n_lines_total, seconds_target=15.0):
     return {"value": rate / 1e9, "unit": "Gray/s", "cores": threads, "kind": "oracle",
             "sample": f"{k2} random lines of the workload, forward + ray-major adjoint "
                       f"(FP64 C/OpenMP), {tf + ta:.1f} s; rate = lines / time",
-            "lines_per_s": rate}
+            "lines_per_s": rate, "cpu": host_cpu_model()}
+
+
+def host_cpu_model() -> str:
+    """The host processor's model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def recon_leg(log):
@@ -319,6 +370,9 @@ def main():
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     ap.add_argument("--valu-calib", action="store_true",
                     help="only run the VALU calibration kernel (known instruction count) and print its issue rate")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="only time the U-Net preconditioner (512x512, 6 levels, 32..256 channels): "
+                         "applies and residual-space training steps (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -349,6 +403,9 @@ def main():
         return
     if args.valu_calib:
         print(json.dumps(valu_calibration(dev)), flush=True)
+        return
+    if args.unet_only:
+        print(json.dumps(unet_timing(dev)), flush=True)
         return
     N, n = args.grid, args.degree
     print(f"[bench] building workload {N}^2 degree {n}", file=sys.stderr, flush=True)
@@ -400,9 +457,9 @@ def main():
     achieved = nnz * F / t_dom / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": measured_traffic("k_adjoint<" if dominant == "adjoint" else "k_forward_persist<"),
+                "traffic": measured_traffic(dominant),
                 "kernel": ("adjoint: k_sort_sino + k_adjoint<3, 1> (vertical lines) + k_adjoint<3, 2> "
-                           "(horizontal lines) + k_adj_reduce after each, timed as one call"
+                           "(horizontal lines) + k_adj_reduce after each + k_adj_nonfinite, timed as one call"
                            if dominant == "adjoint" else
                            "forward: k_layout_v/h + k_forward_persist + k_fwd_reduce, timed as one call"),
                 "frac_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),

@@ -43,19 +43,20 @@ def test_measured_traffic_reads_matching_lines_only(tmp_path, monkeypatch):
     srcs = _fake_tree(tmp_path, "int k;\n")
     sha = bench.kernel_source_hash(srcs)
     (tmp_path / "profiles" / "hbm_traffic_2048_cubic_fan_random.md").write_text(
-        f"    traffic kernel=k_adjoint<3,1> sha={sha} read_bytes=100 write_bytes=20\n"
-        f"    traffic kernel=k_adjoint<3,2> sha={sha} read_bytes=300 write_bytes=40\n"
-        f"    traffic kernel=k_forward<3,true> sha={sha} read_bytes=7 write_bytes=1\n"
-        f"    traffic kernel=k_adjoint<3,1> sha=0000000000000000 read_bytes=999 write_bytes=999\n")
+        f"    traffic call=adjoint kernel=k_adjoint<3,1> count=1 sha={sha} read_bytes=100 write_bytes=20\n"
+        f"    traffic call=adjoint kernel=k_adjoint<3,2> count=1 sha={sha} read_bytes=300 write_bytes=40\n"
+        f"    traffic call=adjoint kernel=k_adj_reduce count=2 sha={sha} read_bytes=5 write_bytes=1\n"
+        f"    traffic call=forward kernel=k_forward<3> count=1 sha={sha} read_bytes=7 write_bytes=1\n"
+        f"    traffic call=adjoint kernel=k_adjoint<3,1> count=1 sha=0000000000000000 read_bytes=999 write_bytes=999\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("k_adjoint") == 460
-    assert bench.measured_traffic("k_forward") == 8
-    assert bench.measured_traffic("k_layout") is None
+    assert bench.measured_traffic("adjoint") == 472
+    assert bench.measured_traffic("forward") == 8
+    assert bench.measured_traffic("layout") is None
     # a code change (not a comment) invalidates the figures
     for p in srcs:
         with open(p, "a") as f:
             f.write("int j;\n")
-    assert bench.measured_traffic("k_adjoint") is None
+    assert bench.measured_traffic("adjoint") is None
 
 
 def test_flops_per_nonzero_counts_one_polynomial_and_one_fma():
