@@ -7,7 +7,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#include <mutex>
 
 #include "xrt_internal.h"
 
@@ -30,68 +29,6 @@ thread_local char g_last_error[256] = "";
 void set_error(const char* what, hipError_t e)
 {
     snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
-}
-
-// ----------------------------------------------------------- E table (FP64)
-// G(z) = sum_l delta_l (z - kappa_l)_+^(2n+1) / (2n+1)!  is the (n+1)-fold
-// integral of beta^n (kappa_l = l - (n+1)/2, delta_l = (-1)^l C(n+1,l));
-// the kernels use g(zeta) = G(-zeta) for zeta in [0, (n+1)/2].  On that range
-// only the knots left of 0 contribute and the terms are O(1), so the sum is
-// well conditioned in FP64.
-double binom(int n, int k)
-{
-    double r = 1.0;
-    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
-    return r;
-}
-
-// sum_l delta_l (z - kappa_l)_+^p / p!.  For p = 0 the step at a knot is
-// taken as its right limit in z when right_limit is set (the value at the
-// knot from z > knot), and as its left limit otherwise.
-double Gpow(int n, double z, int p, bool right_limit = false)
-{
-    double fac = 1.0;
-    for (int i = 2; i <= p; ++i) fac *= i;
-    double acc = 0.0;
-    for (int l = 0; l <= n + 1; ++l) {
-        double x = z - (l - 0.5 * (n + 1));
-        if (x < 0.0 || (x == 0.0 && !(p == 0 && right_limit))) continue;
-        double term = binom(n + 1, l) * (p == 0 ? 1.0 : pow(x, p)) / fac;
-        acc += (l & 1) ? -term : term;
-    }
-    return acc;
-}
-
-float g_tab[4][kTabMax * 4];
-int g_tab_n[4];
-std::once_flag g_tab_once;
-
-void build_tables()
-{
-    for (int n = 0; n <= 3; ++n) {
-        const int nint = kTabPerUnit * (n + 1) / 2;
-        const double dz = 1.0 / kTabPerUnit;
-        for (int i = 0; i < nint; ++i) {
-            // g(zeta) = G(-zeta), g'(zeta) = -G'(-zeta); cubic Hermite in tau.
-            // The end slopes are limits from inside the interval: at zeta0 the
-            // limit from zeta > zeta0 (z < -zeta0), at zeta1 the limit from
-            // zeta < zeta1 (z > -zeta1); they differ only where G' jumps
-            // (degree 0 at the end of the support).
-            const double z0 = i * dz, z1 = (i + 1) * dz;
-            const double g0 = Gpow(n, -z0, 2 * n + 1), g1 = Gpow(n, -z1, 2 * n + 1);
-            const double d0 = -Gpow(n, -z0, 2 * n, false) * dz;
-            const double d1 = -Gpow(n, -z1, 2 * n, true) * dz;
-            const double a0 = g0, a1 = d0;
-            const double a2 = 3.0 * (g1 - g0) - 2.0 * d0 - d1;
-            const double a3 = 2.0 * (g0 - g1) + d0 + d1;
-            g_tab[n][4 * i + 0] = (float)a0;
-            g_tab[n][4 * i + 1] = (float)a1;
-            g_tab[n][4 * i + 2] = (float)a2;
-            g_tab[n][4 * i + 3] = (float)a3;
-        }
-        for (int c = 0; c < 4; ++c) g_tab[n][4 * nint + c] = 0.f;  // |z| >= (n+1)/2
-        g_tab_n[n] = nint + 1;
-    }
 }
 
 bool finite_grid(const xrt_grid& g)
@@ -147,7 +84,7 @@ struct Allocs {
 
 void free_plan_memory(xrt_plan* p, hipStream_t s)
 {
-    void* ptrs[] = {p->xc, p->kap, p->idx, p->off, p->hdr, p->tab,
+    void* ptrs[] = {p->xc, p->kap, p->idx, p->off, p->hdr,
                     p->cv, p->dv, p->ch, p->dh, p->sw, p->part, p->spart, p->fctr, p->adj_part};
     for (void* q : ptrs)
         if (q) (void)hipFreeAsync(q, s);
@@ -158,12 +95,6 @@ void free_plan_memory(xrt_plan* p, hipStream_t s)
 namespace xrt {
 void set_last_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
 
-const float* etable_host(int n, int* n_entries)
-{
-    std::call_once(g_tab_once, build_tables);
-    if (n_entries) *n_entries = g_tab_n[n];
-    return g_tab[n];
-}
 }  // namespace xrt
 
 extern "C" {
@@ -310,7 +241,6 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     p->idx = al.get<int32_t>(m);
     p->off = al.get<uint32_t>(p->key_space + 1);
     p->hdr = al.get<PlanHeader>(1);
-    p->tab = al.get<float4>(kTabMax);
     p->cv = al.get<float>((size_t)g.ny * p->pitch_v);
     p->dv = al.get<float>((size_t)g.ny * p->pitch_v);
     p->ch = al.get<float>((size_t)g.nx * p->pitch_h);
@@ -364,11 +294,7 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
     }
 
     const char* what = "plan";
-    int ntab = 0;
-    const float* tab = etable_host(geom_degree(degree), &ntab);
-    hipError_t e = hipMemcpyAsync(p->tab, tab, sizeof(float) * 4 * ntab, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) what = "table upload";
-    if (e == hipSuccess) e = plan_build(p, lines, t, s, &what);
+    hipError_t e = plan_build(p, lines, t, s, &what);
     PlanHeader h;
     memset(&h, 0, sizeof(h));
     if (e == hipSuccess) {

@@ -14,14 +14,6 @@ namespace xrt {
 constexpr int kPad = 8;
 // Slope bins of the plan (the slope kappa of a line lies in [-1, 1]).
 constexpr int kSlopeBins = 512;
-// Intervals per unit of the knot-transition table.
-// 16 (cubic Hermite error at most 2.7e-8 for degree 3, 3.9e-8 for degree 2,
-// exact for degrees 0 and 1) rather than 64 (1.6e-10): lanes of a wave then
-// read the same entry more often, with fewer LDS bank conflicts (2048^2 cubic
-// adjoint 25.2 -> 24.3 ms, forward 13.8 -> 13.7 ms).
-constexpr int kTabPerUnit = 16;
-// Largest table: degree 3, half-support 2 -> 32 intervals + 1 zero interval.
-constexpr int kTabMax = kTabPerUnit * 2 + 1;
 constexpr int kBlock = 256;
 // Rows per strip of the forward's strip-major schedule (one strip of the
 // coefficient layouts, about 2 MB at 2048 columns, stays in an XCD's L2).
@@ -156,9 +148,6 @@ hipError_t launch_batch_forward(const void* probs, const int2* items, int nitems
 // images); 1: the horizontal lines on the transposed tiles (adds into them)
 hipError_t launch_batch_adjoint(const void* probs, const int2* items, int nitems, unsigned int* counter, int grid,
                                 int horizontal, hipStream_t s);
-// Knot-transition table of degree n (host, FP64-built, rounded to float):
-// kTabPerUnit*(n+1)/2 cubic intervals plus one zero interval, 4 floats each.
-const float* etable_host(int n, int* n_entries);
 
 }  // namespace xrt
 
@@ -189,7 +178,6 @@ struct xrt_plan {
     int32_t* idx;       // original position of the line
     uint32_t* off;      // [key_space + 1] start of every key in sorted order
     xrt::PlanHeader* hdr;
-    float4* tab;        // knot-transition table of this degree
     // workspace
     int pitch_v, pitch_h;
     float *cv, *dv, *ch, *dh;  // coefficient / difference layouts

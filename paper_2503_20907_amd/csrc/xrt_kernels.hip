@@ -340,11 +340,12 @@ __global__ void __launch_bounds__(kBlock) k_layout_h(const float* __restrict__ c
 }
 
 // ---------------------------------------------------------------- row math
-// Constants of one line: kTabPerUnit/r (table units), r^n, the beta'' weight rho, and
-// the number of knot slots S = ceil((n+1) r) (at most n+1) that can be
-// non-zero in a row: only knots within (n+1) r / 2 of the crossing matter.
+// Constants of one line: ka = 1/(A r) with A = (n+1)/2 (the knot argument's
+// scale), r^n, the beta'' weight rho, and the number of knot slots
+// S = ceil((n+1) r) (at most n+1) that can be non-zero in a row: only knots
+// within (n+1) r / 2 of the crossing matter.
 struct LineConst {
-    float inv_tab, rn, rho;
+    float ka, rn, rho;
     int slots;
 };
 
@@ -353,7 +354,7 @@ __device__ inline LineConst line_const(double kap)
 {
     LineConst k;
     const float r = (float)fabs(kap);
-    k.inv_tab = (float)kTabPerUnit / fmaxf(r, 1e-30f);
+    k.ka = 2.f / ((float)(N + 1) * fmaxf(r, 1e-30f));
     float rn = 1.f;
 #pragma unroll
     for (int e = 0; e < N; ++e) rn *= r;
@@ -376,95 +377,111 @@ __device__ inline int wave_slots(int mine)
     return S;
 }
 
-// Knot-transition table at zt = kTabPerUnit z: g(|z|) with the parity of E
-// (E is even for odd n; for even n it changes sign at 0).
-// Table entries are read as a uniform base plus a 32-bit byte offset.  The
-// global copy is typed in the global address space: through a generic pointer
-// the compiler would issue flat loads, whose waits also drain the LDS queue.
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const f4v GTab;
-typedef __attribute__((address_space(1))) const char GByte;
-
-__device__ inline f4v tab_at(const float4* tab, uint32_t byte)
-{
-    const float4 v = *(const float4*)((const char*)tab + byte);
-    return f4v{v.x, v.y, v.z, v.w};
-}
-__device__ inline f4v tab_at(const GTab* tab, uint32_t byte) { return *(const GTab*)((const GByte*)tab + byte); }
-
+// The knot-transition function E in closed form.  E(z) = g(|z|) with the
+// parity of E (even for odd n; for even n it changes sign at 0), and on
+// [0, A], A = (n+1)/2, only the knots kappa_l < 0 of G's truncated-power sum
+// reach g(zeta) = G(-zeta):
+//   n = 0: (1/2 - zeta)_+
+//   n = 1: (1 - zeta)_+^3 / 6
+//   n = 2: ((3/2 - zeta)_+^5 - 3 (1/2 - zeta)_+^5) / 120
+//   n = 3: ((2 - zeta)_+^7 - 4 (1 - zeta)_+^7) / 5040.
+// With w = clamp(1 - zeta/A, 0, 1) and v = clamp(A w - 1, 0, 1) =
+// (A - 1 - zeta)_+ (the inner term, n >= 2): g = knot_scale x with
+// x = w^(2n+1) - knot_inner v^(2n+1).  A knot slot is then VALU work only.
+// A table of E (cubic pieces, 16 per unit, 16-byte entries) was read before:
+// its loads queued on the LDS behind the adjoint's accumulator atomics and
+// on the vector L1, and every row waited for them.  2048^2 cubic: adjoint
+// 24.6 -> 22.0 ms, forward 13.7 -> 13.2 ms, although the adjoint's four-slot
+// row grew from 66 to 70 VALU instructions.  In FP32 the closed form is also
+// closer to E than the table was (2.7e-8 absolute for n = 3).
+//
 // For even n, E jumps at 0 (by P(0): 1 for n = 0, 1/8 for n = 2), and the
 // jump cancels the one of the taps at the same knot.  Which side of the knot
 // the row lies on must therefore be the side the taps take, J = floor(q) in
-// FP64: `right` (q >= K, i.e. z >= 0) comes from the slot's integer offset,
-// not from the sign of the FP32 argument, which rounds to 0 when q lies
-// within ~1e-8 below K (the fraction of q then rounds to 1.0f).
-template <int N, typename T>
-__device__ inline float etab(const T* __restrict__ tab, float zt, bool right)
+// FP64: it comes from the slot's integer offset (knots at or left of J take
+// the sign of z >= 0), not from the sign of the FP32 argument, which rounds
+// to 0 when q lies within ~1e-8 below the knot (the fraction of q then
+// rounds to 1.0f).
+template <int N>
+__device__ constexpr float knot_scale()
 {
-    constexpr int last = kTabPerUnit * (N + 1) / 2;  // index of the zero interval
-    const float a = fminf(fabsf(zt), (float)last);
-    const int i = (int)a;
-    const float tau = __builtin_amdgcn_fractf(a);
-    const f4v cf = tab_at(tab, (uint32_t)i << 4);
-    float g = fmaf(tau, fmaf(tau, fmaf(tau, cf.w, cf.z), cf.y), cf.x);
-    if constexpr (N % 2 == 0) g = right ? -g : g;
-    return g;
+    return N == 0 ? 0.5f : N == 1 ? 1.f / 6.f : N == 2 ? 7.59375f / 120.f : 128.f / 5040.f;
 }
 
-// One row: taps J-d (d = 0..N) at fraction t; knots K0+s (s < S) with E
-// values g[s] (not yet multiplied by r^n).  q = X + (n+1)/2.
-template <int S>
-struct Row {
-    int J, K0;
-    float t;
-    float g[S];
-};
-
-// The two copies of the E table a row reads: knot slots below G take the
-// global copy (through the vector L1 cache), the others the LDS copy.  The
-// forward reads all of them from LDS (G = 0): its vector memory path is busy
-// with the coefficient loads (one or two of the cubic reads through the L1:
-// 2048^2 forward 13.8 -> 19.0 or 23.7 ms).
-struct TabRef {
-    const float4* lds;
-    const GTab* mem;
-};
-
-// The S knot values of a row at fraction t (up: t >= 1/2), not yet
-// multiplied by r^n: z_s = (q - K0 - s)/r with K0 = J + knot_o(up).
-template <int N, int S, int G = 0>
-__device__ inline void row_knots(float t, bool up, const LineConst& k, TabRef tab, float* g)
+template <int N>
+__device__ constexpr float knot_inner()
 {
-    const int o = knot_o<S>(up);
-    // o / r in table units (loop-invariant choices)
-    float oz;
-    if constexpr (S % 2 == 1) {
-        oz = up ? (float)(1 - (S - 1) / 2) * k.inv_tab : (float)(-((S - 1) / 2)) * k.inv_tab;
+    return N == 2 ? 3.f / 7.59375f : N == 3 ? 1.f / 32.f : 0.f;
+}
+
+template <int P>
+__device__ inline float ipow(float w)
+{
+    if constexpr (P == 1) return w;
+    else if constexpr (P == 3) return (w * w) * w;
+    else if constexpr (P == 5) {
+        const float w2 = w * w;
+        return (w2 * w2) * w;
     } else {
-        oz = (float)o * k.inv_tab;
-    }
-    // z_s = (q - K0 - s) / r, in table units; knot K0 + s lies at or left of
-    // q (z_s >= 0) exactly when o + s <= 0
-    const float a0 = fmaf(t, k.inv_tab, -oz);
-    g[0] = G > 0 ? etab<N>(tab.mem, a0, o <= 0) : etab<N>(tab.lds, a0, o <= 0);
-#pragma unroll
-    for (int sl = 1; sl < S; ++sl) {
-        const float z = fmaf(-(float)sl, k.inv_tab, a0);
-        g[sl] = sl < G ? etab<N>(tab.mem, z, o + sl <= 0) : etab<N>(tab.lds, z, o + sl <= 0);
+        const float w2 = w * w;
+        return (w2 * w2) * (w2 * w);
     }
 }
 
-template <int N, int S, int G = 0>
-__device__ inline void row_core(double q, const LineConst& k, TabRef tab, Row<S>& R)
+__device__ inline float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 1.f); }
+
+// x of the knot at distance zeta = A |u| from q.  A knot at least one cell
+// from q (the outer slots: zeta >= 1 since r <= 1) has no inner term.
+template <int N, bool INNER>
+__device__ inline float knot_x(float u)
 {
-    // q > 0 here (a padded or halo-relative column coordinate), so truncation
-    // is the floor
-    const float t = (float)frac_pos(q);
-    R.J = (int)q;
-    R.t = t;
-    const bool up = t >= 0.5f;
-    R.K0 = R.J + knot_o<S>(up);
-    row_knots<N, S, G>(t, up, k, tab, R.g);
+    const float w = clamp01(1.f - fabsf(u));
+    float x = ipow<2 * N + 1>(w);
+    if constexpr (INNER && N >= 2) {
+        const float v = clamp01(fmaf(w, 0.5f * (N + 1), -1.f));
+        x = fmaf(ipow<2 * N + 1>(v), -knot_inner<N>(), x);
+    }
+    return x;
+}
+
+// The S knots nearest to q of a row, K = J + c, and the arguments
+// u_c = (t - c) ka, so that zeta = A |u_c| = |q - K|/r (ka = 1/(A r)):
+//   S = 4: c = -1 .. 2;  S = 3: c = 0, 1, and 2 (t >= 1/2) or -1;
+//   S = 2: c = 0, 1;     S = 1: c = 1 (t >= 1/2) or 0
+// (the slots of knot_o).  The knots with c in {0, 1} are the near ones; the
+// others lie at least one cell from q, so zeta >= 1 (r <= 1) and their inner
+// term vanishes.
+
+// Knots the forward loads per row, and the first one's offset from J.
+template <int S>
+__device__ constexpr int fwd_run() { return S == 3 ? 4 : S; }
+template <int S>
+__device__ inline int fwd_run_o(bool up) { return S == 3 ? -1 : knot_o<S>(up); }
+
+// Forward: sum over the row's knots of E((q - K)/r) D_K / knot_scale.  dv
+// holds D_K for K = J + knot_o<S>(up) + s, s < S, except for S = 3, where it
+// holds the four knots c = -1 .. 2 (fwd_run) so that only the far knot's
+// value is chosen by t >= 1/2.
+template <int N, int S>
+__device__ inline float fwd_knots(float t, bool up, float ka, const float* dv)
+{
+    constexpr bool even = N % 2 == 0;
+    const float u0 = t * ka;
+    if constexpr (S == 1) {
+        const float x = knot_x<N, true>(up ? u0 - ka : u0);
+        return (even ? (up ? x : -x) : x) * dv[0];
+    } else {
+        const float x0 = knot_x<N, true>(u0), x1 = knot_x<N, true>(u0 - ka);
+        if constexpr (S == 2) {
+            return fmaf(x1, dv[1], (even ? -x0 : x0) * dv[0]);
+        } else if constexpr (S == 3) {
+            const float xf = knot_x<N, false>(up ? fmaf(-2.f, ka, u0) : u0 + ka);
+            return fmaf(even ? (up ? xf : -xf) : xf, up ? dv[3] : dv[0], fmaf(x1, dv[2], (even ? -x0 : x0) * dv[1]));
+        } else {
+            const float xm = knot_x<N, false>(u0 + ka), x2 = knot_x<N, false>(fmaf(-2.f, ka, u0));
+            return fmaf(x2, dv[3], fmaf(x1, dv[2], fmaf(even ? -x0 : x0, dv[1], (even ? -xm : xm) * dv[0])));
+        }
+    }
 }
 
 // sum_d w_d(t) c_{J-d} written in powers of t, times kTapScale<N> (c[0] is
@@ -606,7 +623,6 @@ struct FwdArgs {
     const double* xc;
     const double* kap;
     const int32_t* idx;
-    const float4* tab;
     const float* cv;
     const float* dv;
     const float* ch;
@@ -633,11 +649,10 @@ struct FwdArgs {
 // reaches).
 template <int N, int S>
 __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const LineConst& lc,
-                                 const float4* __restrict__ tab, const float* __restrict__ C,
-                                 const float* __restrict__ D, int pitch)
+                                 const float* __restrict__ C, const float* __restrict__ D, int pitch)
 {
     const float rho = lc.rho;
-    const float ern = tap_scale<N>() * lc.rn;
+    const float ernk = tap_scale<N>() * lc.rn * knot_scale<N>();
     // byte offsets (within one strip), so that the loads take the uniform
     // base plus a 32-bit offset
     const char* __restrict__ Cb = (const char*)C;
@@ -658,15 +673,10 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     for (int j = ja; j <= jb; ++j) {
         const float t = (float)tf * 0x1p-32f;
         const bool up = t >= 0.5f;
-        float g[S];
-        row_knots<N, S>(t, up, lc, TabRef{tab, nullptr}, g);
-        float cv[N + 1], dv[S];
+        float cv[N + 1], dv[fwd_run<S>()];
         load_run<N + 1>((const float*)(Cb + (off + (uint32_t)J * 4u)), cv);
-        load_run<S>((const float*)(Db + (off + (uint32_t)(J + knot_o<S>(up) + N) * 4u)), dv);
-        float es = g[0] * dv[0];
-#pragma unroll
-        for (int sl = 1; sl < S; ++sl) es = fmaf(g[sl], dv[sl], es);
-        part += fmaf(ern, es, tap_sum<N>(t, rho, cv));
+        load_run<fwd_run<S>()>((const float*)(Db + (off + (uint32_t)(J + fwd_run_o<S>(up) + N) * 4u)), dv);
+        part += fmaf(ernk, fwd_knots<N, S>(t, up, lc.ka, dv), tap_sum<N>(t, rho, cv));
         const uint32_t tn = tf + Kf;
         J += Ki + (tn < tf ? 1 : 0);
         tf = tn;
@@ -719,8 +729,7 @@ __device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const
 // tap_scale<N>); [*ja, *jb] is that row range (empty when *ja > *jb).  The
 // lanes of a wave that call it together share the knot-slot count.
 template <int N, bool VERT>
-__device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const float4* __restrict__ s_tab,
-                                      int* ja_out, int* jb_out)
+__device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, int* ja_out, int* jb_out)
 {
     const int strip = st;
     const double xc = A.xc[k], kap = A.kap[k];
@@ -757,10 +766,10 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
         const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
         if (ja <= jb) {
             const double q0 = x0 + kap * (double)ja + H + (double)kPad;
-            if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
-            else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
-            else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
-            else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja - r0, jb - r0, lc, s_tab, C, D, pitch);
+            if (S == 1) acc = fwd_walk<N, 1>(q0, kap, ja - r0, jb - r0, lc, C, D, pitch);
+            else if (S == 2) acc = fwd_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, ja - r0, jb - r0, lc, C, D, pitch);
+            else if (S == 3) acc = fwd_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, ja - r0, jb - r0, lc, C, D, pitch);
+            else acc = fwd_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, ja - r0, jb - r0, lc, C, D, pitch);
         }
     }
     *ja_out = ja;
@@ -777,13 +786,6 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, const
 template <int N, bool VERT>
 __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
 {
-    __shared__ float4 s_tab[kTabMax];
-    if constexpr (N != kBox3) {
-        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
-        for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
-        __syncthreads();
-    }
-
     const int strip = A.strip;
     const int bid = blockIdx.x;
     const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
@@ -799,7 +801,7 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     const int64_t k = first + (int64_t)lb * kBlock + threadIdx.x;
     if (k >= end) return;
     int ja, jb;
-    const float acc = fwd_strip_sum<N, VERT>(A, k, strip, s_tab, &ja, &jb);
+    const float acc = fwd_strip_sum<N, VERT>(A, k, strip, &ja, &jb);
     if (strip == 0) A.part[k] = (double)acc;
     else if (ja <= jb) A.part[k] += (double)acc;
 }
@@ -822,19 +824,14 @@ __device__ inline int next_item(unsigned int* counter, int* s_item)
 template <int N>
 __global__ void __launch_bounds__(kBlock) k_forward_persist(FwdArgs A)
 {
-    __shared__ float4 s_tab[kTabMax];
     __shared__ int s_item;
-    if constexpr (N != kBox3) {
-        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
-        for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = A.tab[e];
-    }
     const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
     const int lpi = A.lines_per_item;
     const int64_t nbv = (m_vert + lpi - 1) / lpi;
     const int64_t nbh = (m_valid - m_vert + lpi - 1) / lpi;
     const int64_t items_v = nbv * A.strips_v, items = items_v + nbh * A.strips_h;
     for (;;) {
-        const int it = next_item(A.counter, &s_item);  // synchronises (also after the table load)
+        const int it = next_item(A.counter, &s_item);
         if (it >= items) break;
         const bool vert = it < items_v;   // uniform over the workgroup
         const int64_t li = vert ? it : it - items_v;
@@ -846,8 +843,8 @@ __global__ void __launch_bounds__(kBlock) k_forward_persist(FwdArgs A)
             const int64_t k = first + sub + threadIdx.x;
             if (k < end) {
                 int ja, jb;
-                const float acc = vert ? fwd_strip_sum<N, true>(A, k, st, s_tab, &ja, &jb)
-                                       : fwd_strip_sum<N, false>(A, k, st, s_tab, &ja, &jb);
+                const float acc = vert ? fwd_strip_sum<N, true>(A, k, st, &ja, &jb)
+                                       : fwd_strip_sum<N, false>(A, k, st, &ja, &jb);
                 A.spart[(int64_t)st * A.m + k] = acc;
             }
         }
@@ -908,7 +905,6 @@ struct AdjArgs {
     const double* kap;
     const float* sw;
     const uint32_t* off;
-    const float4* tab;
     int nx, ny;
     int nbk_v, nbk_h, boff_v, boff_h;
     int tiles_i, tiles_j;
@@ -1042,73 +1038,53 @@ __device__ inline void tap_fixed(float t, const TapScaled<N>& k, int* wi)
     }
 }
 
-// Knot slots per row whose E value the adjoint reads from the global table
-// copy (through the vector L1) rather than from LDS.  A row makes N + 1 tap and
-// S knot atomics on LDS, and the S table reads queue behind them there; moving
-// (N + 1)/2 of the reads to the idle L1 shortens the queue (2048^2, 8.85M
-// lines: cubic 32.4 -> 28.3 ms, quadratic 25.4 -> 23.7, linear 18.8 -> 18.1).
-// More than that loads the L1 path instead (three of four cubic reads: no
-// gain; the constant spline, with one atomic pair per row, loses).  The
-// batch's persistent workgroups keep every read on LDS (L1 = false): there the
-// split made the 64-problem adjoint slower, 14.0 -> 15.0 ms.
-template <int N, int S, bool L1>
-__device__ constexpr int adj_mem_slots()
+// One knot atomic: sc is the line's scale (2^e s r^n kKnotScale), negated
+// for the knots at or left of q when n is even (E's parity), and carries the
+// rounding to an integer.
+__device__ inline void knot_add(int* a, float sc, float x) { atomicAdd(a, fixed_round(sc, x)); }
+
+// Adjoint: the row's knot atomics (the slots of fwd_knots), into the knot
+// accumulator at kj (knot J).  For even n the knots with c <= 0 take -sc.
+template <int N, int S>
+__device__ inline void adj_knots(float t, bool up, float ka, float sc, int* kj)
 {
-    return !L1 ? 0 : S < (N + 1) / 2 ? S : (N + 1) / 2;
+    constexpr bool even = N % 2 == 0;
+    const float u0 = t * ka;
+    if constexpr (S == 1) {
+        const float u = up ? u0 - ka : u0;
+        knot_add(kj + (up ? 1 : 0), even ? (up ? sc : -sc) : sc, knot_x<N, true>(u));
+    } else {
+        knot_add(kj, even ? -sc : sc, knot_x<N, true>(u0));
+        knot_add(kj + 1, sc, knot_x<N, true>(u0 - ka));
+        if constexpr (S == 3) {
+            knot_add(kj + (up ? 2 : -1), even ? (up ? sc : -sc) : sc,
+                     knot_x<N, false>(up ? fmaf(-2.f, ka, u0) : u0 + ka));
+        } else if constexpr (S == 4) {
+            knot_add(kj - 1, even ? -sc : sc, knot_x<N, false>(u0 + ka));
+            knot_add(kj + 2, sc, knot_x<N, false>(fmaf(-2.f, ka, u0)));
+        }
+    }
 }
 
-template <int N, int S, bool L1>
-__device__ inline void adj_row(AdjStep st, float svkr, const TapScaled<N>& tk, const LineConst& lc, TabRef s_tab,
-                               int* s_a, int* s_k)
+template <int N, int S>
+__device__ inline void adj_row(AdjStep st, float sck, float ka, const TapScaled<N>& tk, int* s_a, int* s_k)
 {
     // (float) of the low word rounds to nearest and can give t = 1.0 just
     // below a knot: the taps then take the left cell's polynomial at its right
-    // end and the knots their integer side (row_knots), which agree
+    // end and the knots their integer side, which agree
     const float t = (float)st.tf * 0x1p-32f;
     const bool up = t >= 0.5f;
-    // the knot slots' table entries are fetched first (as row_knots forms
-    // them), so that their latency overlaps the tap weights and the tap
-    // atomics (2048^2 cubic adjoint 24.8 -> 24.2 ms)
-    constexpr int G = adj_mem_slots<N, S, L1>();
-    constexpr int last = kTabPerUnit * (N + 1) / 2;
-    const int o = knot_o<S>(up);
-    float oz;
-    if constexpr (S % 2 == 1) {
-        oz = up ? (float)(1 - (S - 1) / 2) * lc.inv_tab : (float)(-((S - 1) / 2)) * lc.inv_tab;
-    } else {
-        oz = (float)o * lc.inv_tab;
-    }
-    const float a0 = fmaf(t, lc.inv_tab, -oz);
-    f4v cf[S];
-    float tau[S];
-#pragma unroll
-    for (int sl = 0; sl < S; ++sl) {
-        const float z = sl == 0 ? a0 : fmaf(-(float)sl, lc.inv_tab, a0);
-        const float a = fminf(fabsf(z), (float)last);
-        const int i = (int)a;
-        tau[sl] = __builtin_amdgcn_fractf(a);
-        cf[sl] = sl < G ? tab_at(s_tab.mem, (uint32_t)i << 4) : tab_at(s_tab.lds, (uint32_t)i << 4);
-    }
     int wi[N + 1];
     tap_fixed<N>(t, tk, wi);
     int* ar = s_a + st.base;  // taps J-N .. J, ascending
-    int* kr = s_k + st.base + (uint32_t)adj_knot_offset<N, S>(up);
 #pragma unroll
     for (int d = 0; d <= N; ++d) atomicAdd(ar + d, wi[N - d]);
-#pragma unroll
-    for (int sl = 0; sl < S; ++sl) {
-        // E at the slot (etab's Horner and parity; o + sl <= 0: knot at or
-        // left of q)
-        float g = fmaf(tau[sl], fmaf(tau[sl], fmaf(tau[sl], cf[sl].w, cf[sl].z), cf[sl].y), cf[sl].x);
-        if constexpr (N % 2 == 0) g = (o + sl <= 0) ? -g : g;
-        atomicAdd(kr + sl, fixed_round(svkr, g));
-    }
+    adj_knots<N, S>(t, up, ka, sck, s_k + st.base + N);
 }
 
-template <int N, int S, bool L1>
+template <int N, int S>
 __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float svs, float svk,
-                                const LineConst& lc, int W, TabRef s_tab,
-                                int* s_a, int* s_k)
+                                const LineConst& lc, int W, int* s_a, int* s_k)
 {
     // start each lane at a different row (spread over [0, cnt) by a
     // multiply and shift) so that the lanes of a wave rarely update the same
@@ -1116,7 +1092,7 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     // neighbouring lanes hold neighbouring lines, and giving them neighbouring
     // rows (l cnt / 64) took 33 ms instead of 25 (2048^2 cubic adjoint).
     const int jj0 = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
-    const float svkr = svk * lc.rn;
+    const float sck = svk * lc.rn * knot_scale<N>();
     const TapScaled<N> tk = tap_scaled<N>(svs, lc.rho);
     // walk q - N (exact): its floor is the first tap J - N (at least 0: the
     // halo covers the footprint), which is the base address of the row; the
@@ -1130,7 +1106,7 @@ __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float 
     const AdjStep st0 = adj_fix_at(F, 0);
     const uint32_t mid = st.base, end = adj_fix_at(F, cnt).base;
     do {
-        adj_row<N, S, L1>(st, svkr, tk, lc, s_tab, s_a, s_k);
+        adj_row<N, S>(st, sck, lc.ka, tk, s_a, s_k);
         adj_fix_next(F, st);
         if (st.base == end) st = st0;
     } while (st.base != mid);
@@ -1192,11 +1168,10 @@ __device__ inline void adj_line_box(const AdjArgs& A, double xck, double kap, bo
     else adj_walk_box<false>(q0, kap, rb - ra + 1, ra - maj0, ldexpf(sv, e), bk, W, s_a);
 }
 
-template <int N, bool L1>
+template <int N>
 __device__ inline void adj_line(const AdjArgs& A, double xck, double kapk, bool active, float sv, int e,
                                 bool vert, int maj0, int min0, int TM, int TN, int nmaj, int W,
-                                double jc, double marg, TabRef s_tab, int* s_a,
-                                int* s_k)
+                                double jc, double marg, int* s_a, int* s_k)
 {
     const double H = 0.5 * (N + 1);
     int ra = 0, rb = -1;
@@ -1221,10 +1196,10 @@ __device__ inline void adj_line(const AdjArgs& A, double xck, double kapk, bool 
     // local q: column index within the LDS row (halo included)
     const double q0 = adj_q0(x0, kap, ra, min0, H);
     const int cnt = rb - ra + 1, row0 = ra - maj0;
-    if (S == 1) adj_walk<N, 1, L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
-    else if (S == 2) adj_walk<N, (N >= 1 ? 2 : 1), L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
-    else if (S == 3) adj_walk<N, (N >= 2 ? 3 : 1), L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
-    else adj_walk<N, (N >= 3 ? 4 : 1), L1>(q0, kap, cnt, row0, svs, svk, lc, W, s_tab, s_a, s_k);
+    if (S == 1) adj_walk<N, 1>(q0, kap, cnt, row0, svs, svk, lc, W, s_a, s_k);
+    else if (S == 2) adj_walk<N, (N >= 1 ? 2 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_a, s_k);
+    else if (S == 3) adj_walk<N, (N >= 2 ? 3 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_a, s_k);
+    else adj_walk<N, (N >= 3 ? 4 : 1)>(q0, kap, cnt, row0, svs, svk, lc, W, s_a, s_k);
 }
 
 __device__ inline float block_max(float v, float* red)
@@ -1247,7 +1222,6 @@ __device__ inline float block_max(float v, float* red)
 struct AdjShared {
     int a[kAccWords];
     int k[kAccWords];
-    float4 tab[kTabMax];
     uint32_t start[kSlopeBins];
     uint32_t pre[kSlopeBins + 1];
     uint32_t scan[kBlock];
@@ -1268,15 +1242,13 @@ template <int MODE>
 __device__ constexpr int adj_tj() { return MODE == kAdjHoriz ? kTileI : kTileJ; }
 
 // One pixel tile of the adjoint; `kpart` selects this workgroup's share of
-// the candidate chunks when A.split > 1.  The table must already be in
-// sh.tab.
-template <int N, int MODE, bool L1 = true>
+// the candidate chunks when A.split > 1.
+template <int N, int MODE>
 __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, AdjShared& sh)
 {
     constexpr int TI = adj_ti<MODE>(), TJ = adj_tj<MODE>();
     int* s_a = sh.a;
     int* s_k = sh.k;
-    const TabRef s_tab{sh.tab, (const GTab*)A.tab};
     uint32_t* s_start = sh.start;
     uint32_t* s_pre = sh.pre;
     uint32_t* s_scan = sh.scan;
@@ -1415,8 +1387,8 @@ __device__ __forceinline__ void adj_tile(const AdjArgs& A, int tile, int kpart, 
                     adj_line_box(A, xcv[u], kpv[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W, jc, marg,
                                  s_a);
                 else
-                    adj_line<N, L1>(A, xcv[u], kpv[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
-                                jc, marg, s_tab, s_a, s_k);
+                    adj_line<N>(A, xcv[u], kpv[u], svv[u] != 0.f, svv[u], e, vert, maj0, min0, TM, TN, nmaj, W,
+                                jc, marg, s_a, s_k);
             }
             __syncthreads();
             // flush: output += (A + Delta^T K) 2^-e  (forward difference of K)
@@ -1465,10 +1437,6 @@ template <int N, int MODE>
 __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
 {
     __shared__ AdjShared sh;
-    if constexpr (N != kBox3) {
-        const int ntab = kTabPerUnit * (N + 1) / 2 + 1;
-        for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
-    }
     const int tile = xcd_logical(blockIdx.x, A.ntiles_pad);
     if (tile >= A.ntiles) return;  // uniform per block
     adj_tile<N, MODE>(A, tile, (int)blockIdx.y, sh);
@@ -1549,18 +1517,18 @@ struct BatchArgs {
 // pixels only that workgroup writes in that launch).
 // Line k over the rows of strip `st` (unscaled sum into spart[st][k]).
 template <int N, bool VERT>
-__device__ inline void fwd_line_strip(const BatchProb& P, int64_t k, int st, const float4* __restrict__ s_tab)
+__device__ inline void fwd_line_strip(const BatchProb& P, int64_t k, int st)
 {
     int ja, jb;
-    P.spart[(int64_t)st * P.f.m + k] = fwd_strip_sum<N, VERT>(P.f, k, st, s_tab, &ja, &jb);
+    P.spart[(int64_t)st * P.f.m + k] = fwd_strip_sum<N, VERT>(P.f, k, st, &ja, &jb);
 }
 
 template <int N>
-__device__ inline void fwd_block_any(const BatchProb& P, int64_t k0, int st, const float4* __restrict__ s_tab)
+__device__ inline void fwd_block_any(const BatchProb& P, int64_t k0, int st)
 {
     const int64_t k = k0 + threadIdx.x;
-    if (k < P.m_vert) fwd_line_strip<N, true>(P, k, st, s_tab);
-    else if (k < P.m_valid) fwd_line_strip<N, false>(P, k, st, s_tab);
+    if (k < P.m_vert) fwd_line_strip<N, true>(P, k, st);
+    else if (k < P.m_valid) fwd_line_strip<N, false>(P, k, st);
 }
 
 // items (problem, strip * blocks + block): the items of one problem are
@@ -1568,21 +1536,13 @@ __device__ inline void fwd_block_any(const BatchProb& P, int64_t k0, int st, con
 // layouts (as in the single-problem schedule)
 __global__ void __launch_bounds__(kBlock) k_batch_forward(BatchArgs B)
 {
-    __shared__ float4 s_tab[kTabMax];
     __shared__ int s_item;
-    int cur = -1;
     for (;;) {
         const int it = next_item(B.counter, &s_item);
         if (it >= B.nitems) break;
         const int2 w = B.items[it];
         const BatchProb& P = B.probs[w.x];
         const int deg = P.degree;
-        if (deg != cur) {   // uniform: all threads read the same item
-            const int ntab = deg == kBox3 ? 0 : kTabPerUnit * (deg + 1) / 2 + 1;
-            for (int e = threadIdx.x; e < ntab; e += kBlock) s_tab[e] = P.f.tab[e];
-            cur = deg;
-            __syncthreads();
-        }
         const int nb = (int)((P.f.m + B.lines_per_item - 1) / B.lines_per_item);
         const int st = w.y / nb, blk = w.y - st * nb;
         const int64_t base = (int64_t)blk * B.lines_per_item;
@@ -1590,11 +1550,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_forward(BatchArgs B)
             const int64_t k0 = base + sub;
             if (k0 >= P.f.m) break;
             switch (deg) {
-            case 0: fwd_block_any<0>(P, k0, st, s_tab); break;
-            case 1: fwd_block_any<1>(P, k0, st, s_tab); break;
-            case 2: fwd_block_any<2>(P, k0, st, s_tab); break;
-            case 3: fwd_block_any<3>(P, k0, st, s_tab); break;
-            default: fwd_block_any<kBox3>(P, k0, st, s_tab); break;
+            case 0: fwd_block_any<0>(P, k0, st); break;
+            case 1: fwd_block_any<1>(P, k0, st); break;
+            case 2: fwd_block_any<2>(P, k0, st); break;
+            case 3: fwd_block_any<3>(P, k0, st); break;
+            default: fwd_block_any<kBox3>(P, k0, st); break;
             }
         }
     }
@@ -1629,26 +1589,18 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_batch_adjoint(BatchArgs
 {
     __shared__ AdjShared sh;
     __shared__ int s_item;
-    int cur = -1;
     for (;;) {
         const int it = next_item(B.counter, &s_item);
         if (it >= B.nitems) break;
         const int2 w = B.items[it];
         const BatchProb& P = B.probs[w.x];
         const AdjArgs& A = MODE == kAdjVert ? P.a : P.ah;
-        const int deg = P.degree;
-        if (deg != cur) {
-            const int ntab = deg == kBox3 ? 0 : kTabPerUnit * (deg + 1) / 2 + 1;
-            for (int e = threadIdx.x; e < ntab; e += kBlock) sh.tab[e] = A.tab[e];
-            cur = deg;
-            __syncthreads();
-        }
-        switch (deg) {
-        case 0: adj_tile<0, MODE, false>(A, w.y, 0, sh); break;
-        case 1: adj_tile<1, MODE, false>(A, w.y, 0, sh); break;
-        case 2: adj_tile<2, MODE, false>(A, w.y, 0, sh); break;
-        case 3: adj_tile<3, MODE, false>(A, w.y, 0, sh); break;
-        default: adj_tile<kBox3, MODE, false>(A, w.y, 0, sh); break;
+        switch (P.degree) {
+        case 0: adj_tile<0, MODE>(A, w.y, 0, sh); break;
+        case 1: adj_tile<1, MODE>(A, w.y, 0, sh); break;
+        case 2: adj_tile<2, MODE>(A, w.y, 0, sh); break;
+        case 3: adj_tile<3, MODE>(A, w.y, 0, sh); break;
+        default: adj_tile<kBox3, MODE>(A, w.y, 0, sh); break;
         }
     }
 }
@@ -1844,7 +1796,6 @@ static FwdArgs make_fwd_args(const xrt_plan* p, float* sino)
     a.xc = p->xc;
     a.kap = p->kap;
     a.idx = p->idx;
-    a.tab = p->tab;
     a.cv = p->cv;
     a.dv = p->dv;
     a.ch = p->ch;
@@ -1876,7 +1827,6 @@ static AdjArgs make_adj_args(const xrt_plan* p, float* out, int mode)
     a.kap = p->kap;
     a.sw = p->sw;
     a.off = p->off;
-    a.tab = p->tab;
     a.nx = p->g.nx;
     a.ny = p->g.ny;
     a.nbk_v = p->nbk_v;

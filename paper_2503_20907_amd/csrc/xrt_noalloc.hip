@@ -12,8 +12,8 @@
 // Each GPU holds its own copy of `scratch` (at its own address) from the
 // first use until the process ends.  Host code never names the array in a
 // kernel argument: at the first call on a device the library looks up that
-// device's address with hipGetSymbolAddress and uploads the knot-transition
-// tables there once; every later use goes through that address.  All calls
+// device's address with hipGetSymbolAddress; every later use goes through
+// that address.  All calls
 // on one GPU share its array: calls that overlap on one GPU (on different
 // streams, or from different threads) race and must be serialised by the
 // caller.
@@ -44,20 +44,10 @@ struct DevScratch {
 };
 DevScratch g_dev[kMaxDevices];
 
-// Knot-transition tables of degrees 0..3 at the start of the array.
-constexpr size_t kTabBytes = 4 * kTabMax * sizeof(float4);
-
 void setup_device(DevScratch& d)
 {
     void* ptr = nullptr;
     d.err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
-    if (d.err != hipSuccess) return;
-    for (int n = 0; n <= 3 && d.err == hipSuccess; ++n) {
-        int ntab = 0;
-        const float* tab = etable_host(n, &ntab);
-        d.err = hipMemcpy((unsigned char*)ptr + (size_t)n * kTabMax * sizeof(float4), tab,
-                          sizeof(float4) * ntab, hipMemcpyHostToDevice);
-    }
     if (d.err == hipSuccess) d.ptr = (unsigned char*)ptr;
 }
 
@@ -118,8 +108,7 @@ extern "C" xrt_status xrt_adjoint_noalloc(const float* sino, const xrt_lines* li
     const int64_t m = p.m;
     // persistent part: line records, bucket offsets, header, sorted sinogram,
     // partial images
-    Carve c{d.ptr, align_up(kTabBytes)};
-    p.tab = degree == kBox3 ? (float4*)d.ptr : (float4*)(d.ptr + (size_t)degree * kTabMax * sizeof(float4));
+    Carve c{d.ptr, 0};
     p.hdr = c.take<PlanHeader>(1);
     p.xc = c.take<double>(m);
     p.kap = c.take<double>(m);
