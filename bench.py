@@ -119,6 +119,39 @@ def valu_calibration(dev, iters: int = 2048, blocks_per_cu: int = 8):
     return res
 
 
+def lds_calibration(dev, iters: int = 256, blocks_per_cu: int = 5):
+    """LDS cost of a wave64 32-bit integer atomic (xrt_calib_lds): for each
+    address pattern the time per atomic wave instruction per compute unit,
+    in cycles at 2.4 GHz (the counters of the same run give the clock)."""
+    import torch
+
+    from paper_2503_20907_amd import _lib as L
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks = cus * blocks_per_cu
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    names = ["consecutive", "stride2", "stride32", "same_word", "hashed", "stride64", "pairs", "stride65",
+             "u64_consecutive", "u64_hashed"]
+    res = {"cus": cus, "blocks": blocks, "iters": iters, "atomics_per_thread": 16 * iters}
+    for pat, name in enumerate(names):
+        for _ in range(2):
+            assert L.xrt_calib_lds(pat, iters, blocks, out.data_ptr(), stream.cuda_stream) == 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 5
+        for _ in range(reps):
+            L.xrt_calib_lds(pat, iters, blocks, out.data_ptr(), stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        per_cu = blocks * 4 * 16 * iters / cus
+        cyc = t * 2.4e9 / per_cu
+        res[name] = {"ms": round(t * 1e3, 4), "cycles_per_atomic_per_cu": round(cyc, 3)}
+        print(f"[bench] lds calibration {name}: {t * 1e3:.3f} ms, {cyc:.3f} cycles per wave atomic "
+              f"per CU at 2.4 GHz", file=sys.stderr, flush=True)
+    return res
+
+
 def unet_timing(dev, applies: int = 10, steps: int = 5, batch: int = 4):
     """The reconstruction workload's U-Net (512 x 512, 6 levels, 32..256
     channels, random weights): mean time of an apply and of a residual-space
@@ -368,6 +401,8 @@ def main():
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
+    ap.add_argument("--lds-calib", action="store_true",
+                    help="time xrt_calib_lds (LDS atomic cost per address pattern) and exit")
     ap.add_argument("--valu-calib", action="store_true",
                     help="only run the VALU calibration kernel (known instruction count) and print its issue rate")
     ap.add_argument("--unet-only", action="store_true",
@@ -403,6 +438,9 @@ def main():
         return
     if args.valu_calib:
         print(json.dumps(valu_calibration(dev)), flush=True)
+        return
+    if args.lds_calib:
+        print(json.dumps(lds_calibration(dev)), flush=True)
         return
     if args.unet_only:
         print(json.dumps(unet_timing(dev)), flush=True)

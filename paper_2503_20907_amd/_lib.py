@@ -46,6 +46,7 @@ EXPORTS = (
     "xrt_batch_autotune",
     # xrt_bench.h
     "xrt_calib_valu",
+    "xrt_calib_lds",
 )
 
 
@@ -111,6 +112,8 @@ def load() -> ctypes.CDLL:
     lib.xrt_adjoint_noalloc.argtypes = [vp, ctypes.POINTER(XrtLines), i32, XrtGrid, vp, vp]
     lib.xrt_calib_valu.argtypes = [i32, i32, i32, vp, vp]
     lib.xrt_calib_valu.restype = i32
+    lib.xrt_calib_lds.argtypes = [i32, i32, i32, vp, vp]
+    lib.xrt_calib_lds.restype = i32
     lib.xrt_plan_create.argtypes = [XrtGrid, i32, ctypes.POINTER(XrtLines), vp,
                                     ctypes.POINTER(vp)]
     lib.xrt_plan_forward.argtypes = [vp, vp, vp, vp]
@@ -206,6 +209,10 @@ def xrt_adjoint_noalloc(sino, lines: XrtLines, degree: int, grid: XrtGrid, coeff
 
 def xrt_calib_valu(mode: int, iters: int, blocks: int, out, stream) -> int:
     return load().xrt_calib_valu(int(mode), int(iters), int(blocks), out, stream)
+
+
+def xrt_calib_lds(pattern: int, iters: int, blocks: int, out, stream) -> int:
+    return load().xrt_calib_lds(int(pattern), int(iters), int(blocks), out, stream)
 
 
 def xrt_plan_create(grid: XrtGrid, degree: int, lines: XrtLines, stream):
