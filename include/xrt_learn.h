@@ -123,6 +123,22 @@ xrt_status xrt_unet_loss_grad_normal(xrt_unet* net, const xrt_plan* plan, float 
 xrt_status xrt_unet_train_step_normal(xrt_unet* net, const xrt_plan* plan, float lambda, const float* r,
                                       int32_t batch, float lr, float* loss, void* stream);
 
+/* Energy-norm loss for the normal equations of `plan`, on pairs (r_b, e_b)
+ * with r_b = M e_b:
+ *     loss = (1/batch) sum_b (N(r_b) - e_b)^T M (N(r_b) - e_b) / e_b^T M e_b,
+ * the squared M-norm of the error left by one step x += N(r), relative to
+ * the error's (the norm conjugate gradients minimise, Section IV-B's
+ * solver; the residual-space loss above is its M^2-weighted counterpart).
+ * The curvature in the network's output is M rather than M^2, and the
+ * gradient w.r.t. N(r_b) is 2 (M N(r_b) - r_b) / (batch e_b^T r_b): one
+ * application of M per image.  e: [batch][H][W] device floats.  Temporary
+ * device memory is allocated stream-ordered.  Errors: EPLAN, EINVAL, ESIZE. */
+xrt_status xrt_unet_loss_grad_energy(xrt_unet* net, const xrt_plan* plan, float lambda, const float* r,
+                                     const float* e, int32_t batch, float* loss, float* grad, void* stream);
+/* xrt_unet_loss_grad_energy followed by one Adam step (as xrt_unet_train_step). */
+xrt_status xrt_unet_train_step_energy(xrt_unet* net, const xrt_plan* plan, float lambda, const float* r,
+                                      const float* e, int32_t batch, float lr, float* loss, void* stream);
+
 /* Building blocks of the network, exposed for testing.  bf16 arrays are raw
  * 16-bit patterns; x [B][H][W][cin], w [9][cout][cin] (tap = 3 ky + kx),
  * gy [B][H][W][cout], outputs fp32.  cin and cout are multiples of 32.

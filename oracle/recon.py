@@ -272,11 +272,17 @@ def _relu(a):
     return np.maximum(a, 0.0)
 
 
-def unet_forward(flat, x, levels, base):
+def _ident(a):
+    return a
+
+
+def unet_forward(flat, x, levels, base, relu=True):
     """Network output for a batch of images x [B][H][W] (no normalisation).
+    relu=False: the same network without its activations (a linear map).
 
     Returns (y [B][H][W], cache of every intermediate needed by the backward).
     """
+    act = _relu if relu else _ident
     p = unpack(flat, levels, base)
     a = np.asarray(x, dtype=np.float64)[..., None]
     cache = {"x": a}
@@ -285,28 +291,28 @@ def unet_forward(flat, x, levels, base):
         if l > 0:
             a = avgpool2(enc[-1])
         cache[f"in{l}"] = a
-        h = _relu(conv3x3(a, p[f"enc{l}a"]))
+        h = act(conv3x3(a, p[f"enc{l}a"]))
         cache[f"enc{l}h"] = h
-        e = _relu(conv3x3(h, p[f"enc{l}b"]))
+        e = act(conv3x3(h, p[f"enc{l}b"]))
         enc.append(e)
     cache["enc"] = enc
     d = enc[-1]
     for l in range(levels - 2, -1, -1):
         cache[f"dec{l}in"] = d
-        uc = _relu(conv3x3(d, p[f"dec{l}up"]))
+        uc = act(conv3x3(d, p[f"dec{l}up"]))
         cache[f"dec{l}uc"] = uc
         cat = np.concatenate([enc[l], upsample2(uc)], axis=3)
         cache[f"dec{l}cat"] = cat
-        h = _relu(conv3x3(cat, p[f"dec{l}a"]))
+        h = act(conv3x3(cat, p[f"dec{l}a"]))
         cache[f"dec{l}h"] = h
-        d = _relu(conv3x3(h, p[f"dec{l}b"]))
+        d = act(conv3x3(h, p[f"dec{l}b"]))
         cache[f"dec{l}d"] = d
     cache["last"] = d
     y = d @ p["out"]
     return y, cache
 
 
-def unet_backward(flat, cache, gy, levels, base):
+def unet_backward(flat, cache, gy, levels, base, relu=True):
     """Gradient of sum(gy * y) with respect to the flat parameter vector.
 
     Walks the forward in reverse: the 1x1 output, the decoder from the finest
@@ -316,6 +322,8 @@ def unet_backward(flat, cache, gy, levels, base):
     summed before that level is processed.
     """
     p = unpack(flat, levels, base)
+    # derivative of the activation at a stored output (1 everywhere without)
+    act = (lambda a: a > 0) if relu else (lambda a: 1.0)
     g = {}
     gy = np.asarray(gy, dtype=np.float64)
     g["out"] = np.einsum("bhwc,bhw->c", cache["last"], gy)
@@ -323,33 +331,33 @@ def unet_backward(flat, cache, gy, levels, base):
     enc = cache["enc"]
     genc = [np.zeros_like(e) for e in enc]
     for l in range(levels - 1):                   # decoder, fine to coarse
-        gpre = gd * (cache[f"dec{l}d"] > 0)
+        gpre = gd * act(cache[f"dec{l}d"])
         g[f"dec{l}b"] = conv3x3_grad_weight(cache[f"dec{l}h"], gpre)
-        gh = conv3x3_grad_input(gpre, p[f"dec{l}b"]) * (cache[f"dec{l}h"] > 0)
+        gh = conv3x3_grad_input(gpre, p[f"dec{l}b"]) * act(cache[f"dec{l}h"])
         g[f"dec{l}a"] = conv3x3_grad_weight(cache[f"dec{l}cat"], gh)
         gcat = conv3x3_grad_input(gh, p[f"dec{l}a"])
         c = enc[l].shape[3]
         genc[l] += gcat[..., :c]
-        guc = upsample2_T(gcat[..., c:]) * (cache[f"dec{l}uc"] > 0)
+        guc = upsample2_T(gcat[..., c:]) * act(cache[f"dec{l}uc"])
         g[f"dec{l}up"] = conv3x3_grad_weight(cache[f"dec{l}in"], guc)
         gd = conv3x3_grad_input(guc, p[f"dec{l}up"])   # gradient of decoder level l+1's output
     genc[levels - 1] += gd                        # the coarsest "decoder output" is the encoder's
     for l in range(levels - 1, -1, -1):           # encoder, coarse to fine
-        gpre = genc[l] * (enc[l] > 0)
+        gpre = genc[l] * act(enc[l])
         g[f"enc{l}b"] = conv3x3_grad_weight(cache[f"enc{l}h"], gpre)
-        gh = conv3x3_grad_input(gpre, p[f"enc{l}b"]) * (cache[f"enc{l}h"] > 0)
+        gh = conv3x3_grad_input(gpre, p[f"enc{l}b"]) * act(cache[f"enc{l}h"])
         g[f"enc{l}a"] = conv3x3_grad_weight(cache[f"in{l}"], gh)
         if l > 0:
             genc[l - 1] += avgpool2_T(conv3x3_grad_input(gh, p[f"enc{l}a"]))
     return pack(g, levels, base)
 
 
-def precondition(flat, r, levels, base, gain=1.0):
+def precondition(flat, r, levels, base, gain=1.0, relu=True):
     """The learned preconditioner z = N(r) for a batch r [B][H][W]:
     N(r) = gain * rms(r) * UNet(r / rms(r)) per image (rms over its pixels)."""
     r = np.asarray(r, dtype=np.float64)
     rms = np.sqrt(np.mean(r * r, axis=(1, 2)))
-    y, _ = unet_forward(flat, r / rms[:, None, None], levels, base)
+    y, _ = unet_forward(flat, r / rms[:, None, None], levels, base, relu)
     return gain * y * rms[:, None, None]
 
 
@@ -405,3 +413,30 @@ def precond_loss_normal(flat, r, levels, base, n, line_cs, lam, gain=1.0, nx=Non
         gz = 2.0 * normal_apply(n, d, line_cs, lam) / (B * rr)
         gy[b] = gz * gain * rms[b]
     return loss, unet_backward(flat, cache, gy, levels, base)
+
+
+def precond_loss_energy(flat, r, e, levels, base, n, line_cs, lam, gain=1.0, relu=True):
+    """Energy-norm training loss for the normal equations and its gradient.
+
+    For pairs r_b = M e_b (M = H^T H + lam L^T L, the oracle's transform):
+    loss = mean_b (z_b - e_b)^T M (z_b - e_b) / e_b^T M e_b with z_b = N(r_b),
+    the squared M-norm of the error one step x += N(r) leaves, relative to the
+    error's (conjugate gradients minimise this norm).  Written out with
+    q_b = M z_b: (z^T q - 2 z^T r + e^T r) / e^T r, whose gradient w.r.t. z_b
+    is 2 (q_b - r_b) / (B e_b^T r_b) (M is symmetric); z_b = gain rms(r_b)
+    UNet(r_b / rms(r_b)) carries it to the network output.
+    """
+    r = np.asarray(r, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    B = r.shape[0]
+    rms = np.sqrt(np.mean(r * r, axis=(1, 2)))
+    y, cache = unet_forward(flat, r / rms[:, None, None], levels, base, relu)
+    z = gain * y * rms[:, None, None]
+    gy = np.zeros_like(y)
+    loss = 0.0
+    for b in range(B):
+        q = normal_apply(n, z[b], line_cs, lam)
+        er = float(np.sum(e[b] * r[b]))
+        loss += (float(np.sum(z[b] * q)) - 2.0 * float(np.sum(z[b] * r[b])) + er) / er / B
+        gy[b] = 2.0 * (q - r[b]) / (B * er) * gain * rms[b]
+    return loss, unet_backward(flat, cache, gy, levels, base, relu)

@@ -37,7 +37,8 @@ EXPORTS = (
     "xrt_reg_apply", "xrt_normal_apply", "xrt_unet_create", "xrt_unet_destroy", "xrt_unet_num_params",
     "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_set_gain", "xrt_unet_get_gain",
     "xrt_unet_set_relu", "xrt_unet_apply", "xrt_unet_loss_grad", "xrt_unet_train_step",
-    "xrt_unet_loss_grad_normal", "xrt_unet_train_step_normal", "xrt_conv3x3_forward",
+    "xrt_unet_loss_grad_normal", "xrt_unet_train_step_normal", "xrt_unet_loss_grad_energy",
+    "xrt_unet_train_step_energy", "xrt_conv3x3_forward",
     "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve", "xrt_solve_ex", "xrt_sino_filter",
     "xrt_solve_sino_pcg",
     # xrt_batch.h
@@ -144,6 +145,8 @@ def load() -> ctypes.CDLL:
     lib.xrt_unet_train_step.argtypes = [vp, vp, vp, i32, f32, vp, vp]
     lib.xrt_unet_loss_grad_normal.argtypes = [vp, vp, f32, vp, i32, vp, vp, vp]
     lib.xrt_unet_train_step_normal.argtypes = [vp, vp, f32, vp, i32, f32, vp, vp]
+    lib.xrt_unet_loss_grad_energy.argtypes = [vp, vp, f32, vp, vp, i32, vp, vp, vp]
+    lib.xrt_unet_train_step_energy.argtypes = [vp, vp, f32, vp, vp, i32, f32, vp, vp]
     lib.xrt_conv3x3_forward.argtypes = [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp]
     lib.xrt_conv3x3_grad_input.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
     lib.xrt_conv3x3_grad_weight.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
@@ -175,7 +178,8 @@ def load() -> ctypes.CDLL:
                  "xrt_normal_apply", "xrt_unet_create", "xrt_unet_num_params",
                  "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_apply",
                  "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
-                 "xrt_unet_train_step_normal", "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve",
+                 "xrt_unet_train_step_normal", "xrt_unet_loss_grad_energy", "xrt_unet_train_step_energy",
+                 "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve",
                  "xrt_solve_ex", "xrt_sino_filter", "xrt_solve_sino_pcg"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -324,6 +328,14 @@ def xrt_unet_loss_grad_normal(net, plan, lam, r, batch, loss, grad, stream) -> i
 
 def xrt_unet_train_step_normal(net, plan, lam, r, batch, lr, loss, stream) -> int:
     return load().xrt_unet_train_step_normal(net, plan, float(lam), r, int(batch), float(lr), loss, stream)
+
+
+def xrt_unet_loss_grad_energy(net, plan, lam, r, e, batch, loss, grad, stream) -> int:
+    return load().xrt_unet_loss_grad_energy(net, plan, float(lam), r, e, int(batch), loss, grad, stream)
+
+
+def xrt_unet_train_step_energy(net, plan, lam, r, e, batch, lr, loss, stream) -> int:
+    return load().xrt_unet_train_step_energy(net, plan, float(lam), r, e, int(batch), float(lr), loss, stream)
 
 
 def xrt_conv3x3_forward(x, w, B, H, W, cin, cout, relu, y, stream) -> int:

@@ -650,6 +650,53 @@ xrt_status xrt_unet_train_step_normal(xrt_unet* net, const xrt_plan* plan, float
     return adam_update(net, lr, (hipStream_t)stream);
 }
 
+xrt_status xrt_unet_loss_grad_energy(xrt_unet* net, const xrt_plan* plan, float lambda, const float* r,
+                                     const float* e_in, int32_t batch, float* loss, float* grad, void* stream)
+{
+    if (!net_ok(net) || !r || !e_in || !loss || batch < 1 || batch > net->maxB) return XRT_EINVAL;
+    int64_t m = 0, crossing = 0;
+    xrt_status st = xrt_plan_info(plan, &m, &crossing);
+    if (st != XRT_OK) return st;
+    if (plan->g.nx != net->W || plan->g.ny != net->H) return XRT_ESIZE;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t npix = (int64_t)net->H * net->W, nb = (int64_t)batch * npix;
+    // workspace: z, q (= M z), d (= q - r); sinogram; per-image sums; the
+    // per-image partial sums of the three dot products
+    float* ws = nullptr;
+    const int64_t ms = m > 0 ? m : 1;
+    const int64_t parts = 3 * (int64_t)xrl::image_parts() * batch;
+    XL_CHECK(hipMallocAsync((void**)&ws, (3 * nb + ms + 2 * (int64_t)batch) * sizeof(float) + parts * sizeof(double),
+                            s),
+             "hipMallocAsync");
+    float *z = ws, *q = ws + nb, *d = ws + 2 * nb, *sino = ws + 3 * nb;
+    float *er = sino + ms, *lb = er + batch;
+    double* part = (double*)(ws + 3 * nb + ms + 2 * (int64_t)batch);
+    hipError_t e = forward(net, r, nullptr, batch, s);
+    if (e == hipSuccess) e = xrl::unscale(net->y, net->scale, batch, npix, net->gain, z, s);
+    for (int b = 0; b < batch && e == hipSuccess && st == XRT_OK; ++b)
+        st = xrt_normal_apply(plan, lambda, z + b * npix, q + b * npix, sino, stream);
+    if (e == hipSuccess && st == XRT_OK) e = xrl::energy_stats(z, q, r, e_in, d, batch, npix, er, lb, loss, part, s);
+    if (grad && e == hipSuccess && st == XRT_OK) {
+        e = xrl::resid_grad(d, net->scale, er, batch, npix, net->gain, net->gy, s);
+        if (e == hipSuccess) e = backward(net, r, batch, s);
+        if (e == hipSuccess && grad != net->grad)
+            e = hipMemcpyAsync(grad, net->grad, net->nparam * sizeof(float), hipMemcpyDeviceToDevice, s);
+    }
+    (void)hipFreeAsync(ws, s);
+    if (e != hipSuccess) return hip_fail("unet energy loss", e);
+    return st;
+}
+
+xrt_status xrt_unet_train_step_energy(xrt_unet* net, const xrt_plan* plan, float lambda, const float* r,
+                                      const float* e, int32_t batch, float lr, float* loss, void* stream)
+{
+    if (!(lr > 0.f)) return XRT_EINVAL;
+    xrt_status st = xrt_unet_loss_grad_energy(net, plan, lambda, r, e, batch, loss,
+                                              net_ok(net) ? net->grad : nullptr, stream);
+    if (st != XRT_OK) return st;
+    return adam_update(net, lr, (hipStream_t)stream);
+}
+
 static xrt_status check_conv_args(const void* a, const void* b, int32_t B, int32_t H, int32_t W, int32_t cin,
                                   int32_t cout, const void* out)
 {

@@ -629,6 +629,50 @@ __global__ void k_resid_stats(const double* part, int B, float* rr, float* lb)
     lb[b] = sr > 0.0 ? (float)(sd / sr) : 0.f;
 }
 
+// Energy-norm loss: d = q - r (q = M z); part[b][blk] = (sum z q, sum z r,
+// sum e r) over a slice of image b (grid: kImgParts x B)
+__global__ __launch_bounds__(256) void k_energy_sums(const float* z, const float* q, const float* r, const float* e,
+                                                     float* d, int64_t npix, double* part)
+{
+    __shared__ double sh[4];
+    const int b = blockIdx.y;
+    double zq = 0.0, zr = 0.0, er = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npix; p += (int64_t)kImgParts * 256) {
+        const int64_t i = (int64_t)b * npix + p;
+        const float qi = q[i], ri = r[i], zi = z[i];
+        d[i] = qi - ri;
+        zq += (double)zi * qi;
+        zr += (double)zi * ri;
+        er += (double)e[i] * ri;
+    }
+    zq = block_sum(zq, sh);
+    zr = block_sum(zr, sh);
+    er = block_sum(er, sh);
+    if (threadIdx.x == 0) {
+        double* o = part + ((int64_t)b * kImgParts + blockIdx.x) * 3;
+        o[0] = zq;
+        o[1] = zr;
+        o[2] = er;
+    }
+}
+
+// one thread per image: er[b] = e^T r = e^T M e; lb[b] = (z - e)^T M (z - e) / e^T M e
+//   = (z^T q - 2 z^T r + e^T r) / e^T r
+__global__ void k_energy_stats(const double* part, int B, float* er, float* lb)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double zq = 0.0, zr = 0.0, eer = 0.0;
+    for (int k = 0; k < kImgParts; ++k) {
+        const double* o = part + ((int64_t)b * kImgParts + k) * 3;
+        zq += o[0];
+        zr += o[1];
+        eer += o[2];
+    }
+    er[b] = (float)eer;
+    lb[b] = eer > 0.0 ? (float)((zq - 2.0 * zr + eer) / eer) : 0.f;
+}
+
 // gy = md * 2 gain / (scale[b] * B * rr[b])
 __global__ void k_resid_grad(const float* md, const float* scale, const float* rr, int B, int64_t npix, float gain,
                              float* gy)
@@ -993,6 +1037,15 @@ hipError_t resid_stats(const float* q, const float* r, float* d, int B, int64_t 
 {
     hipLaunchKernelGGL(k_resid_sums, dim3(kImgParts, B), dim3(256), 0, s, q, r, d, npix, part);
     hipLaunchKernelGGL(k_resid_stats, dim3(nblk(B, 64)), dim3(64), 0, s, part, B, rr, lb);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, lb, B, B, loss);
+    return hipGetLastError();
+}
+
+hipError_t energy_stats(const float* z, const float* q, const float* r, const float* e, float* d, int B,
+                        int64_t npix, float* er, float* lb, float* loss, double* part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_sums, dim3(kImgParts, B), dim3(256), 0, s, z, q, r, e, d, npix, part);
+    hipLaunchKernelGGL(k_energy_stats, dim3(nblk(B, 64)), dim3(64), 0, s, part, B, er, lb);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, lb, B, B, loss);
     return hipGetLastError();
 }

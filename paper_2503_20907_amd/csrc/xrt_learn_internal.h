@@ -92,6 +92,12 @@ hipError_t loss_grad(const float* y, const float* e, const float* scale, const f
 // residual-space loss: d = q - r, rr[b] = ||r_b||^2, lb[b] = ||d_b||^2 / rr[b], *loss = mean_b lb[b]
 hipError_t resid_stats(const float* q, const float* r, float* d, int B, int64_t npix, float* rr, float* lb,
                        float* loss, double* part, hipStream_t s);
+// energy-norm loss: d = q - r, er[b] = e_b^T r_b (= e_b^T M e_b), lb[b] =
+// (z_b - e_b)^T M (z_b - e_b) / er[b] from q = M z, *loss = mean_b lb[b];
+// part: 3 * image_parts() * B doubles.  Its gradient w.r.t. the network
+// output is resid_grad(d, scale, er, ...) (M symmetric: 2 (M z - r) / er).
+hipError_t energy_stats(const float* z, const float* q, const float* r, const float* e, float* d, int B,
+                        int64_t npix, float* er, float* lb, float* loss, double* part, hipStream_t s);
 // its gradient w.r.t. the normalised network output: gy = md * 2 gain / (scale[b] B rr[b])
 hipError_t resid_grad(const float* md, const float* scale, const float* rr, int B, int64_t npix, float gain,
                       float* gy, hipStream_t s);

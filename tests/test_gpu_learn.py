@@ -257,15 +257,122 @@ def test_residual_loss_and_gradient_match_oracle(dev, learn):
     plan.close()
 
 
+# ---------------------------------------------------------- energy-norm loss
+@pytest.mark.parametrize("relu", [True, False])
+def test_energy_loss_and_gradient_match_oracle(dev, learn, relu):
+    from paper_2503_20907_amd import ops
+    print(f"energy loss 32x32 degree 1 relu={relu}", flush=True)
+    n, N, lam, levels, base = 1, 32, 0.05, 3, 32
+    rng = np.random.default_rng(54)
+    th = rng.uniform(0, math.pi, 300).astype(np.float32)
+    y = rng.uniform(-20, 20, 300).astype(np.float32)
+    spec = {"kind": "theta_y", "theta": th, "y": y}
+    lc = oracle.lines(spec)
+    plan = ops.Plan(N, N, n, ops.Lines.from_spec(spec))
+    shapes = [s for _, s in R.unet_layout(levels, base)]
+    p = W.unet_params(shapes, seed=55)
+    net = learn.UNet(N, N, levels=levels, base=base, max_batch=2, seed=0, relu=relu)
+    net.set_params(torch.as_tensor(p, device=dev))
+    net.gain = 0.05
+    e = W.training_fields(2, N, N, seed=56).numpy().astype(np.float64)
+    # exact pairs r = M e by the oracle's operator, rounded to FP32
+    r = np.stack([R.normal_apply(n, e[b], lc, lam) for b in range(2)]).astype(np.float32)
+    e32 = e.astype(np.float32)
+    loss, grad = net.loss_grad_energy(plan, lam, torch.as_tensor(r, device=dev), torch.as_tensor(e32, device=dev))
+    loss_ref, grad_ref = R.precond_loss_energy(_bf16_round(p), r.astype(np.float64), e32.astype(np.float64),
+                                               levels, base, n, lc, lam, gain=0.05, relu=relu)
+    assert abs(float(loss) - loss_ref) < 2e-2 * loss_ref
+    g = grad.cpu().numpy()
+    assert rel(g, grad_ref) < 4e-2
+    assert float(np.dot(g, grad_ref) / (np.linalg.norm(g) * np.linalg.norm(grad_ref))) > 0.999
+    z = net.apply(torch.as_tensor(r, device=dev)).cpu().numpy()
+    zref = R.precondition(_bf16_round(p), r.astype(np.float64), levels, base, gain=0.05, relu=relu)
+    assert rel(z, zref) < 4e-2
+    net.close()
+    plan.close()
+
+
+# --------------------------------------------------- reproducible training
+def test_training_is_reproducible_from_its_seed(dev, learn):
+    """Two trainings with the same seed give bit-identical parameters (plans,
+    pairs, mini-batches, kernels and reductions are all deterministic); a
+    different seed gives different ones."""
+    from paper_2503_20907_amd import ops
+    print("training reproducibility 64^2", flush=True)
+    N, n, lam = 64, 3, 1e-2
+    spec = W.parallel_beam(45, 96)
+    plan = ops.Plan(N, N, n, ops.Lines.from_spec(spec))
+    fields = W.training_fields(16, N, N, seed=71, device=dev)
+    val = W.training_fields(2, N, N, seed=72, device=dev)
+    params = []
+    for seed in (5, 5, 6):
+        for relu, loss in ((False, "energy"), (True, "residual")):
+            net, st = learn.train_preconditioner(plan, lam, fields, levels=3, base=32, max_channels=32, steps=60,
+                                                 rounds=2, refresh=8, seed=seed, lr=2e-4, relu=relu, loss=loss,
+                                                 warmup=10, val_fields=val)
+            params.append(net.get_params().cpu())
+            net.close()
+    assert torch.equal(params[0], params[2]) and torch.equal(params[1], params[3])
+    assert not torch.equal(params[0], params[4]) and not torch.equal(params[1], params[5])
+    plan.close()
+
+
+# ---------------------------------------- the learned solver against plain CG
+def test_linear_preconditioner_beats_cg_on_the_reconstruction_workload(dev, learn):
+    """The reconstruction workload (512^2 cubic B-spline, 180 x 768 parallel
+    beam, Poisson data at 1e4 photons, lambda = 1e-2, x0 = 0) with the
+    preconditioner trained by learn.LINEAR_RECIPE (fixed seed): flexible CG
+    with the network on every step reaches relative residual 1e-3 in fewer
+    steps and less wall time than plain CG (median of three solves each), and
+    both solutions meet 1e-3 by the FP64 oracle's operator."""
+    import time
+    from paper_2503_20907_amd import ops
+    print("learned vs CG 512^2 cubic", flush=True)
+    N, n, lam = 512, 3, 1e-2
+    spec, c_true = W.recon_problem(N, 180, 768)
+    lc = oracle.lines(spec)
+    p = W.noisy_log_data(oracle.forward(n, c_true, lc), photons=1e4, peak=3.0)
+    b64 = oracle.adjoint(n, p.astype(np.float64), lc, N, N)
+    b = torch.as_tensor(b64.astype(np.float32), device=dev)
+    plan = ops.Plan(N, N, n, ops.Lines.from_spec(spec))
+    fields = W.training_fields(800, N, N, seed=3, device=dev)
+    net, st = learn.train_preconditioner(plan, lam, fields, **learn.LINEAR_RECIPE,
+                                         val_fields=W.training_fields(8, N, N, seed=11, device=dev))
+    del fields
+    res = {}
+    for name, kw in (("cg", {}), ("learned", {"net": net, "window": 8, "period": 1})):
+        runs = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = learn.solve(plan, b, lam, tol=1e-3, maxit=500, **kw)
+            torch.cuda.synchronize()
+            runs.append(((time.perf_counter() - t0) * 1e3, info, x))
+        runs.sort(key=lambda v: v[0])
+        ms, info, x = runs[1]
+        xo = x.cpu().numpy().astype(np.float64)
+        bo = b64.astype(np.float32).astype(np.float64)
+        true_res = np.linalg.norm(bo - R.normal_apply(n, xo, lc, lam)) / np.linalg.norm(bo)
+        assert info["converged"] and true_res <= 1.02e-3, (name, true_res)
+        res[name] = (ms, info["iterations"])
+        print(f"{name}: {info['iterations']} steps, {ms:.2f} ms, residual {true_res:.2e}", flush=True)
+    print(f"train {st['train_s']:.1f} s, round {st['kept_round']} kept", flush=True)
+    assert res["learned"][1] < res["cg"][1]
+    assert res["learned"][0] < res["cg"][0]
+    net.close()
+    plan.close()
+
+
 # --------------------------------------------- what the trained network gains
 def test_trained_preconditioner_gain(dev, learn):
     """Train the preconditioner on a 128^2 cubic problem with operator-made
     pairs, then compare flexible CG with the network against plain CG on the
     problem's own right-hand side (noisy parallel-beam data).  The network's
-    steps reduce the residual faster than CG's first steps (by 10% at least
-    after two steps: training follows the operator's FP32 rounding, and runs
-    have given 0.77-0.83 of CG's residual); both runs reach 1e-3, checked with
-    the FP64 oracle's operator."""
+    steps reduce the residual faster than CG's first steps: training is
+    deterministic for its seed and leaves 0.545 of CG's residual after two
+    steps; the bound 0.6 leaves room for changes in the operator's FP32
+    rounding, which training follows.  Both runs reach 1e-3, checked with the
+    FP64 oracle's operator."""
     from paper_2503_20907_amd import ops
     print("trained preconditioner 128^2 cubic", flush=True)
     N, n, lam = 128, 3, 1e-2
@@ -283,7 +390,7 @@ def test_trained_preconditioner_gain(dev, learn):
     _, fl2 = learn.solve(plan, b, lam, tol=1e-30, maxit=2, net=net, history=2)
     print(f"after 2 steps: CG {cg2['history'][-1]:.4f}, learned {fl2['history'][-1]:.4f}; "
           f"train {stats['train_s']:.1f} s", flush=True)
-    assert fl2["history"][-1] < 0.9 * cg2["history"][-1]
+    assert fl2["history"][-1] < 0.6 * cg2["history"][-1]
     res = {}
     for name, kw in (("cg", {}), ("learned", {"net": net, "window": 8, "period": 1})):
         torch.cuda.synchronize()

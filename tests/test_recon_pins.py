@@ -217,6 +217,71 @@ def test_residual_loss_gradient_matches_central_differences():
     assert abs(loss - ref) < 1e-12 * ref
 
 
+@pytest.mark.parametrize("relu", [True, False])
+def test_energy_loss_gradient_matches_central_differences(relu):
+    # the energy-norm loss chains the network with the normal operator once
+    n, N, lam, levels, base = 1, 8, 0.05, 2, 2
+    rng = _rng(16)
+    th = rng.uniform(0, math.pi, 10).astype(np.float32)
+    y = rng.uniform(-4, 4, 10).astype(np.float32)
+    lc = oracle.lines_from_theta_y(th, y)
+    shapes = [s for _, s in R.unet_layout(levels, base)]
+    nprm = sum(int(np.prod(s)) for s in shapes)
+    flat = rng.normal(size=nprm) * 0.5
+    e = rng.normal(size=(2, N, N))
+    r = np.stack([R.normal_apply(n, e[b], lc, lam) for b in range(2)])
+    loss, g = R.precond_loss_energy(flat, r, e, levels, base, n, lc, lam, gain=0.3, relu=relu)
+    h = 1e-6
+    for k in rng.choice(nprm, 25, replace=False):
+        fp, fm = flat.copy(), flat.copy()
+        fp[k] += h
+        fm[k] -= h
+        fd = (R.precond_loss_energy(fp, r, e, levels, base, n, lc, lam, 0.3, relu)[0]
+              - R.precond_loss_energy(fm, r, e, levels, base, n, lc, lam, 0.3, relu)[0]) / (2 * h)
+        assert abs(g[k] - fd) < 1e-6 * max(1.0, abs(fd)), (k, g[k], fd)
+
+
+def test_energy_loss_is_the_m_norm_of_the_step_error():
+    # by the dense matrix M = H^T H + lam L^T L: loss = mean (z-e)^T M (z-e) / e^T M e
+    # for pairs r = M e, z = N(r); an exact inverse (z = e) gives 0, z = 0 gives 1
+    n, N, lam, levels, base = 1, 6, 0.05, 2, 2
+    lc, H = _tiny_problem(n, N)
+    Lt = np.stack([R.reg_apply(np.eye(N * N)[k].reshape(N, N), 1.0).ravel() for k in range(N * N)], axis=1)
+    Md = H.T @ H + lam * Lt
+    rng = _rng(17)
+    shapes = [s for _, s in R.unet_layout(levels, base)]
+    flat = rng.normal(size=sum(int(np.prod(s)) for s in shapes)) * 0.5
+    e = rng.normal(size=(3, N, N))
+    r = np.stack([(Md @ e[b].ravel()).reshape(N, N) for b in range(3)])
+    for relu in (True, False):
+        loss, _ = R.precond_loss_energy(flat, r, e, levels, base, n, lc, lam, gain=0.7, relu=relu)
+        z = R.precondition(flat, r, levels, base, gain=0.7, relu=relu)
+        ref = np.mean([(z[b] - e[b]).ravel() @ Md @ (z[b] - e[b]).ravel() / (e[b].ravel() @ Md @ e[b].ravel())
+                       for b in range(3)])
+        assert abs(loss - ref) < 1e-10 * ref
+    # the out layer set to zero: N = 0, the step leaves the whole error
+    flat0 = flat.copy()
+    flat0[-base:] = 0.0
+    loss0, _ = R.precond_loss_energy(flat0, r, e, levels, base, n, lc, lam, gain=0.7, relu=False)
+    assert abs(loss0 - 1.0) < 1e-12
+
+
+def test_linear_unet_is_a_linear_map():
+    # without activations every layer is linear and there are no biases, so
+    # N(a r1 + b r2) = a N(r1) + b N(r2) (the rms normalisation cancels);
+    # with ReLU it is not
+    rng = _rng(18)
+    shapes = [s for _, s in R.unet_layout(3, 2)]
+    flat = rng.normal(size=sum(int(np.prod(s)) for s in shapes))
+    r1, r2 = rng.normal(size=(1, 8, 8)), rng.normal(size=(1, 8, 8))
+    lin = R.precondition(flat, 2.0 * r1 - 3.0 * r2, 3, 2, relu=False)
+    assert np.allclose(lin, 2.0 * R.precondition(flat, r1, 3, 2, relu=False)
+                       - 3.0 * R.precondition(flat, r2, 3, 2, relu=False), rtol=1e-10, atol=1e-10)
+    nl = R.precondition(flat, 2.0 * r1 - 3.0 * r2, 3, 2)
+    assert not np.allclose(nl, 2.0 * R.precondition(flat, r1, 3, 2) - 3.0 * R.precondition(flat, r2, 3, 2),
+                           rtol=1e-3, atol=1e-3)
+
+
 # ------------------------------------------------- sinogram filter preconditioner
 def test_sino_filter_matches_scipy_correlate1d():
     from scipy.ndimage import correlate1d
