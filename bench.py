@@ -153,25 +153,28 @@ def lds_calibration(dev, iters: int = 256, blocks_per_cu: int = 5):
 
 
 def unet_timing(dev, applies: int = 10, steps: int = 5, batch: int = 4):
-    """The reconstruction workload's U-Net (512 x 512, 6 levels, 32..256
-    channels, random weights): mean time of an apply and of a residual-space
-    training step (batch 4: forward, loss through the normal operator,
-    backward, Adam), for profiling the network's kernels."""
+    """The reconstruction workload's preconditioner network (512 x 512, the
+    linear U-Net of learn.LINEAR_RECIPE, random weights): mean time of an
+    apply and of an energy-norm training step (batch 4: forward, loss through
+    the normal operator, backward, Adam), for profiling the network's
+    kernels."""
     import torch
 
     import xrt_workloads as W
     from paper_2503_20907_amd import learn, ops
     N, lam = 512, 1e-2
+    rc = learn.LINEAR_RECIPE
     spec, _ = W.recon_problem(N, 180, 768)
     plan = ops.Plan(N, N, 3, ops.Lines.from_spec(spec))
-    net = learn.UNet(N, N, levels=6, base=32, max_batch=batch, seed=1, max_channels=256)
+    net = learn.UNet(N, N, levels=rc["levels"], base=rc["base"], max_batch=batch, seed=1,
+                     max_channels=rc["max_channels"], relu=rc["relu"])
     fields = W.training_fields(batch, N, N, seed=3, device=dev)
     R = learn.make_pairs(plan, lam, fields)
     net.gain = learn.typical_gain(R, fields)
     z = torch.empty_like(R[0])
     for _ in range(2):
         net.apply(R[0], z)
-        net.train_step_normal(plan, lam, R, 1e-5)
+        net.train_step_energy(plan, lam, R, fields, 1e-5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(applies):
@@ -179,7 +182,7 @@ def unet_timing(dev, applies: int = 10, steps: int = 5, batch: int = 4):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(steps):
-        net.train_step_normal(plan, lam, R, 1e-5)
+        net.train_step_energy(plan, lam, R, fields, 1e-5)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     out = {"apply_ms": round((t1 - t0) / applies * 1e3, 4), "train_step_ms": round((t2 - t1) / steps * 1e3, 4),
