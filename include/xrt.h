@@ -29,9 +29,11 @@
  *     outputs must not alias.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
  *     Entry points that create a plan (xrt_plan_create, and xrt_forward /
- *     xrt_adjoint, which build a temporary plan) synchronise with `stream` once
- *     to read the plan header back; xrt_plan_forward / xrt_plan_adjoint do not
- *     synchronise.
+ *     xrt_adjoint, which build a temporary plan) synchronise with `stream` once,
+ *     during plan creation, to read the plan header back (that is where
+ *     degenerate or non-finite lines are found); they do not wait for the
+ *     transform itself.  xrt_plan_forward / xrt_plan_adjoint and
+ *     xrt_adjoint_noalloc do not synchronise.
  *   - Argument errors are returned synchronously before any work is enqueued.
  *     A failing HIP call returns XRT_EHIP; xrt_last_error() then gives the HIP
  *     message for the calling thread.
@@ -99,12 +101,15 @@ typedef struct {
 typedef struct xrt_plan xrt_plan;
 
 /* Forward projection (eq. (4)) of coeffs [g.ny][g.nx] along every line into
- * sino [lines->n].  Builds and frees a temporary plan (synchronises once). */
+ * sino [lines->n].  Builds a temporary plan (synchronising once, in its
+ * creation) and frees it stream-ordered after the launches. */
 xrt_status xrt_forward(const float* coeffs, xrt_grid g, int degree, const xrt_lines* lines,
                        float* sino, void* stream);
 
-/* Adjoint (back-projection) of sino [lines->n] into coeffs_out [g.ny][g.nx].
- * Builds and frees a temporary plan (synchronises once). */
+/* Adjoint (back-projection, the transpose of H of Section IV-A, as in
+ * Section II-B) of sino [lines->n] into coeffs_out [g.ny][g.nx].  Builds a
+ * temporary plan (synchronising once, in its creation) and frees it
+ * stream-ordered after the launches. */
 xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xrt_grid g,
                        float* coeffs_out, void* stream);
 
@@ -116,8 +121,8 @@ xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xr
  * on holds until the process ends (about 56 B per line, 8 B per
  * (orientation, slope bin, crossing bucket) key and up to 8 partial images:
  * e.g. 700,000 lines on a 512^2 grid); larger problems return XRT_ESIZE.
- * The first call on a device sets the array up (looks up its address and
- * uploads the footprint tables, synchronously).  Every call on one GPU
+ * The first call on a device sets the array up (looks up its address,
+ * synchronously).  Every call on one GPU
  * shares that array: calls that overlap on one GPU race and must be
  * serialised by the caller.  Degenerate or non-finite lines are not
  * reported (that needs a synchronisation); they contribute nothing.
@@ -135,10 +140,17 @@ xrt_status xrt_adjoint_noalloc(const float* sino, const xrt_lines* lines, int de
 xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream,
                            xrt_plan** out);
 
-/* Forward / adjoint with a plan: the hot path.  No synchronisation, no
- * allocation.  Repeated calls with one plan give bitwise-identical results,
- * and so do two plans built from the same lines (the plan's sort is stable:
- * lines of one bucket keep their input order). */
+/* Forward / adjoint with a plan: the hot path.  xrt_plan_forward computes
+ * eq. (4), s_m = sum_k c_k h phi_theta_m((y_m - <x_k, theta_m_perp>)/h), for
+ * every line of the plan into sino [n] (the caller's line order);
+ * xrt_plan_adjoint computes its exact transpose (Section II-B: the
+ * back-projection with the same footprint) of sino [n] into
+ * coeffs_out [ny][nx], overwriting it.  coeffs/sino/coeffs_out are
+ * caller-owned device arrays; work is enqueued on `stream`.  No
+ * synchronisation, no allocation.  Repeated calls with one plan give
+ * bitwise-identical results, and so do two plans built from the same lines
+ * (the plan's sort is stable: lines of one bucket keep their input order).
+ * Errors: XRT_EPLAN (not a plan), XRT_EINVAL (null array), XRT_EHIP. */
 xrt_status xrt_plan_forward(const xrt_plan* p, const float* coeffs, float* sino, void* stream);
 xrt_status xrt_plan_adjoint(const xrt_plan* p, const float* sino, float* coeffs_out,
                             void* stream);

@@ -412,10 +412,9 @@ xrt_status xrt_forward(const float* coeffs, xrt_grid g, int degree, const xrt_li
     st = xrt_plan_create(g, degree, lines, stream, &p);
     if (st != XRT_OK) return st;
     st = xrt_plan_forward(p, coeffs, sino, stream);
-    hipStream_t s = (hipStream_t)stream;
-    (void)hipStreamSynchronize(s);
-    free_plan_memory(p, s);
-    (void)hipStreamSynchronize(s);
+    // stream-ordered frees: the memory is released once the launches above
+    // have run, without waiting here
+    free_plan_memory(p, (hipStream_t)stream);
     p->magic = 0;
     delete p;
     return st;
@@ -435,10 +434,9 @@ xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xr
     st = xrt_plan_create(g, degree, lines, stream, &p);
     if (st != XRT_OK) return st;
     st = xrt_plan_adjoint(p, sino, coeffs_out, stream);
-    hipStream_t s = (hipStream_t)stream;
-    (void)hipStreamSynchronize(s);
-    free_plan_memory(p, s);
-    (void)hipStreamSynchronize(s);
+    // stream-ordered frees: the memory is released once the launches above
+    // have run, without waiting here
+    free_plan_memory(p, (hipStream_t)stream);
     p->magic = 0;
     delete p;
     return st;
