@@ -189,6 +189,25 @@ XRT_HD inline int adj_knot_offset(bool up)
     return knot_o<S>(up) + N;
 }
 
+// Start row (0 .. cnt-1) of the lane's walk over its cnt rows: lanes of a
+// wave start at rows spread by a multiply and shift of the scrambled lane
+// index (M l mod 64), so that neighbouring lanes, which hold neighbouring
+// lines, rarely update the same LDS word in one instruction.  M = 19 for the
+// B-splines: a simulation of the 2048^2 benchmark tiles' LDS address streams
+// (the plan's candidate order, every atomic's address, the cost per
+// half-wave measured with xrt_calib_lds) gave 5.66 cycles per atomic with
+// 19 against 6.00 with 37 (and 5.6-6.7 over 100 multiplier and pitch pairs);
+// the cubic adjoint went from 22.2 to 21.6 ms.  Neighbouring rows for
+// neighbouring lanes (l cnt / 64) took a third longer.
+template <unsigned M>
+XRT_HD inline int adj_start_row(unsigned lane, int cnt)
+{
+    return (int)((((lane * M) & 63u) * (unsigned)cnt) >> 6);
+}
+
+// the multiplier (also for the box spline's rows: 10.75 -> 10.62 ms with 19)
+constexpr unsigned kAdjSpread = 19u;
+
 // The adjoint walks a line's rows in 32.32 fixed point: Q(jj) = Q0 + jj Kq
 // with Q0 = round((q - n) 2^32) at the line's first row in the tile and
 // Kq = round(kappa 2^32), so that floor(q - n) (the first tap's column) is

@@ -1086,12 +1086,8 @@ template <int N, int S>
 __device__ inline void adj_walk(double q0, double kap, int cnt, int row0, float svs, float svk,
                                 const LineConst& lc, int W, int* s_a, int* s_k)
 {
-    // start each lane at a different row (spread over [0, cnt) by a
-    // multiply and shift) so that the lanes of a wave rarely update the same
-    // LDS word in one instruction.  The lane index is scrambled (37 l mod 64):
-    // neighbouring lanes hold neighbouring lines, and giving them neighbouring
-    // rows (l cnt / 64) took 33 ms instead of 25 (2048^2 cubic adjoint).
-    const int jj0 = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
+    // start each lane at a different row (adj_start_row)
+    const int jj0 = adj_start_row<kAdjSpread>(threadIdx.x, cnt);
     const float sck = svk * lc.rn * knot_scale<N>();
     const TapScaled<N> tk = tap_scaled<N>(svs, lc.rho);
     // walk q - N (exact): its floor is the first tap J - N (at least 0: the
@@ -1122,7 +1118,7 @@ __device__ inline void adj_walk_box(double q0, double kap, int cnt, int row0, fl
     // start row spread and fixed-point walk as in adj_walk, on q - 1: its
     // floor is the first column floor(q) - 1 (columns floor(q) - 1 ..
     // floor(q) + 2)
-    const int jj0 = (int)((((threadIdx.x * 37u) & 63u) * (unsigned)cnt) >> 6);
+    const int jj0 = adj_start_row<kAdjSpread>(threadIdx.x, cnt);
     const AdjFix F = adj_fix(q0 - 1.0, kap, row0, W);
     AdjStep st = adj_fix_at(F, jj0);
     const AdjStep st0 = adj_fix_at(F, 0);

@@ -3,7 +3,8 @@
 // For random lines on several grids, every (pixel tile, line) pair of both
 // adjoint passes goes through the same functions the kernels use
 // (canon_core, adj_rows, adj_q0, the fixed-point walk adj_fix / adj_fix_at /
-// adj_fix_next, adj_tap_base, adj_knot_offset, from xrt_geom.h), and every
+// adj_fix_next, adj_start_row, adj_tap_base, adj_knot_offset, from
+// xrt_geom.h), and every
 // accumulator word a row would update is checked to lie inside its own
 // accumulator row: taps and knot slots in [0, W) of row (row0 + jj), rows in
 // [0, TM).  The walk must visit every row once, wrap and end on the
@@ -44,7 +45,7 @@ static void walk_bspline(double xc, double kap, const AdjRows& rr, int maj0, int
     const AdjFix F = adj_fix(q0 - (double)N, kap, row0, W);
     const uint32_t end = adj_fix_at(F, cnt).base;
     for (int lane = 0; lane < 64; lane += 7) {
-        const int jj0 = (int)((((unsigned)lane * 37u) & 63u) * (unsigned)cnt >> 6);
+        const int jj0 = adj_start_row<kAdjSpread>((unsigned)lane, cnt);
         AdjStep st = adj_fix_at(F, jj0);
         const uint32_t mid = st.base;
         int jj = jj0, steps = 0;
@@ -110,7 +111,7 @@ static void line_tile_box(double xc, double kap, int nmaj, int nmin, int maj0, i
     const AdjFix F = adj_fix(q0 - 1.0, kap, row0, W);
     const uint32_t end = adj_fix_at(F, cnt).base;
     for (int lane = 0; lane < 64; lane += 7) {
-        const int jj0 = (int)((((unsigned)lane * 37u) & 63u) * (unsigned)cnt >> 6);
+        const int jj0 = adj_start_row<kAdjSpread>((unsigned)lane, cnt);
         AdjStep st = adj_fix_at(F, jj0);
         const AdjStep st0 = adj_fix_at(F, 0);
         const uint32_t mid = st.base;
