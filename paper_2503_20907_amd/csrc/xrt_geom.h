@@ -173,7 +173,7 @@ XRT_HD inline uint32_t mul24(uint32_t a, uint32_t b)
 // q = X + (n+1)/2: the S knots nearest to q, centred on round(q) for odd S
 // (up: the fraction of q is at least 1/2) and on q for even S.
 template <int S>
-XRT_HD inline int knot_o(bool up)
+XRT_HD constexpr int knot_o(bool up)
 {
     if constexpr (S % 2 == 0) {
         return 1 - S / 2;

@@ -456,7 +456,7 @@ __device__ inline float knot_x(float u)
 template <int S>
 __device__ constexpr int fwd_run() { return S == 3 ? 4 : S; }
 template <int S>
-__device__ inline int fwd_run_o(bool up) { return S == 3 ? -1 : knot_o<S>(up); }
+__device__ constexpr int fwd_run_o(bool up) { return S == 3 ? -1 : knot_o<S>(up); }
 
 // Forward: sum over the row's knots of E((q - K)/r) D_K / knot_scale.  dv
 // holds D_K for K = J + knot_o<S>(up) + s, s < S, except for S = 3, where it
@@ -656,9 +656,14 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     // byte offsets (within one strip), so that the loads take the uniform
     // base plus a 32-bit offset
     const char* __restrict__ Cb = (const char*)C;
-    const char* __restrict__ Db = (const char*)D;
+    // the knot run's first knot lies at a fixed offset from J for S >= 2
+    // (fwd_run_o), folded into the uniform base
+    constexpr int kFixedRun = S >= 2 ? (fwd_run_o<S>(false) + N) * 4 : 0;
+    const char* __restrict__ Db = (const char*)D + kFixedRun;
     uint32_t off = (uint32_t)ja * (uint32_t)pitch * 4u;
     const uint32_t step = (uint32_t)pitch * 4u;
+    // the row offset ends the walk (ja <= jb here)
+    const uint32_t off_end = off + (uint32_t)(jb - ja + 1) * step;
     float part = 0.f;
     // walk q - N: its floor is the first tap J - N, so that the taps and the
     // knot slots (at J - N + N + o) share one offset register.  The walk is
@@ -670,18 +675,20 @@ __device__ inline float fwd_walk(double q, double kap, int ja, int jb, const Lin
     const int Ki = (int)(Kq >> 32);
     uint32_t tf = (uint32_t)Q0;
     int J = (int)(Q0 >> 32);
-    for (int j = ja; j <= jb; ++j) {
+    do {
         const float t = (float)tf * 0x1p-32f;
         const bool up = t >= 0.5f;
         float cv[N + 1], dv[fwd_run<S>()];
-        load_run<N + 1>((const float*)(Cb + (off + (uint32_t)J * 4u)), cv);
-        load_run<fwd_run<S>()>((const float*)(Db + (off + (uint32_t)(J + fwd_run_o<S>(up) + N) * 4u)), dv);
+        const uint32_t o = off + (uint32_t)J * 4u;
+        load_run<N + 1>((const float*)(Cb + o), cv);
+        if constexpr (S >= 2) load_run<fwd_run<S>()>((const float*)(Db + o), dv);
+        else load_run<1>((const float*)(Db + (o + (uint32_t)(fwd_run_o<S>(up) + N) * 4u)), dv);
         part += fmaf(ernk, fwd_knots<N, S>(t, up, lc.ka, dv), tap_sum<N>(t, rho, cv));
         const uint32_t tn = tf + Kf;
         J += Ki + (tn < tf ? 1 : 0);
         tf = tn;
         off += step;
-    }
+    } while (off != off_end);
     return part;
 }
 
