@@ -318,6 +318,7 @@ def test_training_is_reproducible_from_its_seed(dev, learn):
 
 
 # ---------------------------------------- the learned solver against plain CG
+@pytest.mark.timeout(400)
 def test_linear_preconditioner_beats_cg_on_the_reconstruction_workload(dev, learn):
     """The reconstruction workload (512^2 cubic B-spline, 180 x 768 parallel
     beam, Poisson data at 1e4 photons, lambda = 1e-2, x0 = 0) with the
