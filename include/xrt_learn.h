@@ -90,6 +90,16 @@ xrt_status xrt_unet_get_gain(const xrt_unet* net, float* gain);
  * none (a linear network).  Set it before training.  Errors: EINVAL. */
 xrt_status xrt_unet_set_relu(xrt_unet* net, int32_t on);
 
+/* Launch fusion of xrt_unet_apply (on = 1, the default): the 2x2 average
+ * pooling before each encoder level and the nearest-neighbour upsampling and
+ * concatenation before each decoder level are read inside the convolutions
+ * that consume them, and the output unscaling inside the last layer, instead
+ * of being written out by kernels of their own (the layers listed at the top
+ * of this file).  The values are the same bit for bit; on = 0 restores the separate
+ * kernels, as a test hook.  Training always writes the activations out, since
+ * the backward pass reads them.  Errors: EINVAL (on not 0 or 1). */
+xrt_status xrt_unet_set_fusion(xrt_unet* net, int32_t on);
+
 /* z = N(r) for `batch` images r [batch][height][width] (fp32).  An image of
  * zeros maps to zeros.  Errors: EINVAL (batch out of range, null). */
 xrt_status xrt_unet_apply(xrt_unet* net, const float* r, float* z, int32_t batch, void* stream);

@@ -36,7 +36,7 @@ EXPORTS = (
     # xrt_learn.h
     "xrt_reg_apply", "xrt_normal_apply", "xrt_unet_create", "xrt_unet_destroy", "xrt_unet_num_params",
     "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_set_gain", "xrt_unet_get_gain",
-    "xrt_unet_set_relu", "xrt_unet_apply", "xrt_unet_loss_grad", "xrt_unet_train_step",
+    "xrt_unet_set_relu", "xrt_unet_set_fusion", "xrt_unet_apply", "xrt_unet_loss_grad", "xrt_unet_train_step",
     "xrt_unet_loss_grad_normal", "xrt_unet_train_step_normal", "xrt_unet_loss_grad_energy",
     "xrt_unet_train_step_energy", "xrt_conv3x3_forward",
     "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve", "xrt_solve_ex", "xrt_sino_filter",
@@ -140,6 +140,7 @@ def load() -> ctypes.CDLL:
     lib.xrt_unet_set_gain.argtypes = [vp, f32]
     lib.xrt_unet_get_gain.argtypes = [vp, ctypes.POINTER(f32)]
     lib.xrt_unet_set_relu.argtypes = [vp, i32]
+    lib.xrt_unet_set_fusion.argtypes = [vp, i32]
     lib.xrt_unet_apply.argtypes = [vp, vp, vp, i32, vp]
     lib.xrt_unet_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     lib.xrt_unet_train_step.argtypes = [vp, vp, vp, i32, f32, vp, vp]
@@ -177,7 +178,7 @@ def load() -> ctypes.CDLL:
                  "xrt_plan_adjoint", "xrt_plan_info", "xrt_plan_nnz", "xrt_reg_apply",
                  "xrt_normal_apply", "xrt_unet_create", "xrt_unet_num_params",
                  "xrt_unet_set_params", "xrt_unet_get_params", "xrt_unet_apply",
-                 "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
+                 "xrt_unet_set_gain", "xrt_unet_get_gain", "xrt_unet_set_relu", "xrt_unet_set_fusion", "xrt_unet_loss_grad", "xrt_unet_train_step", "xrt_unet_loss_grad_normal",
                  "xrt_unet_train_step_normal", "xrt_unet_loss_grad_energy", "xrt_unet_train_step_energy",
                  "xrt_conv3x3_forward", "xrt_conv3x3_grad_input", "xrt_conv3x3_grad_weight", "xrt_solve",
                  "xrt_solve_ex", "xrt_sino_filter", "xrt_solve_sino_pcg"):
@@ -302,6 +303,10 @@ def xrt_unet_set_gain(net, gain) -> int:
 
 def xrt_unet_set_relu(net, on) -> int:
     return load().xrt_unet_set_relu(net, int(on))
+
+
+def xrt_unet_set_fusion(net, on) -> int:
+    return load().xrt_unet_set_fusion(net, int(on))
 
 
 def xrt_unet_get_gain(net):

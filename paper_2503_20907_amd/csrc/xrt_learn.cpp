@@ -51,6 +51,7 @@ struct xrt_unet {
     int64_t step;
     float gain;     // fixed output gain: N(r) = gain * rms(r) * U(r / rms(r))
     bool relu;      // activation after every 3x3 convolution (false: a linear network)
+    bool fuse = true;   // xrt_unet_apply reads pooled / upsampled inputs inside the convolutions
     // activations, per level (see forward())
     Buf in[8], eh[8], cat[8], ebot, uc[8], dh[8], dd[8];
     // gradients
@@ -153,10 +154,12 @@ View genc_w(xrt_unet* n, int l) { return l == n->L - 1 ? n->gebot.v() : n->gcat[
 CView dec_out(const xrt_unet* n, int l) { return l == n->L - 1 ? n->ebot.cv() : n->dd[l].cv(); }
 
 hipError_t conv(xrt_unet* n, CView x, const uint16_t* w, View y, CView mask, int B, int H, int W, int cin, int cout,
-                bool relu, hipStream_t s)
+                bool relu, hipStream_t s, int in_mode = xrl::kConvPlain, CView x2 = CView{nullptr, 0})
 {
     xrl::ConvArgs a;
     a.x = x;
+    a.in_mode = in_mode;
+    a.x2 = x2;
     a.w = w;
     a.y = y.p;
     a.ypitch = y.pitch;
@@ -201,9 +204,14 @@ hipError_t repack(xrt_unet* n, hipStream_t s)
     return hipSuccess;
 }
 
-// network forward for B images r [B][H][W]; leaves y (normalised output) and all activations
-hipError_t forward(xrt_unet* n, const float* r, const float* e, int B, hipStream_t s)
+// network forward for B images r [B][H][W]; leaves y (normalised output) and all activations.
+// With z != nullptr (an apply: no backward follows) the output is unscaled into z instead of
+// y, and with n->fuse the pooled encoder inputs and the upsampled halves of the decoder's
+// concatenations are read inside the convolutions that consume them (same values, fewer
+// launches) and not written out.
+hipError_t forward(xrt_unet* n, const float* r, const float* e, int B, hipStream_t s, float* z = nullptr)
 {
+    const bool fuse = z && n->fuse;
     const int L = n->L;
     const int64_t npix = (int64_t)n->H * n->W;
     const CView none{nullptr, 0};
@@ -218,6 +226,9 @@ hipError_t forward(xrt_unet* n, const float* r, const float* e, int B, hipStream
         const int H = n->H >> l, W = n->W >> l, c = n->ch[l];
         if (l == 0) {
             XL_RUN(xrl::conv_in(r, n->scale, WF(n, enc_a(n, 0)), n->eh[0].v(), c, B, H, W, n->relu, s));
+        } else if (fuse) {
+            XL_RUN(conv(n, enc_out(n, l - 1), WF(n, enc_a(n, l)), n->eh[l].v(), none, B, H, W, n->ch[l - 1], c,
+                        n->relu, s, xrl::kConvPool));
         } else {
             XL_RUN(xrl::avgpool2(enc_out(n, l - 1), n->in[l].v(), n->ch[l - 1], B, H * 2, W * 2, s));
             XL_RUN(conv(n, n->in[l].cv(), WF(n, enc_a(n, l)), n->eh[l].v(), none, B, H, W, n->ch[l - 1], c, n->relu, s));
@@ -229,11 +240,21 @@ hipError_t forward(xrt_unet* n, const float* r, const float* e, int B, hipStream
         const int H = n->H >> l, W = n->W >> l, c = n->ch[l];
         XL_RUN(conv(n, dec_out(n, l + 1), WF(n, dec_up(n, l)), n->uc[l].v(), none, B, H / 2, W / 2, n->ch[l + 1], c,
                     n->relu, s));
-        XL_RUN(xrl::upsample2(n->uc[l].cv(), n->cat[l].v(c), c, B, H, W, s));
-        XL_RUN(conv(n, n->cat[l].cv(), WF(n, dec_a(n, l)), n->dh[l].v(), none, B, H, W, 2 * c, c, n->relu, s));
+        if (fuse) {
+            XL_RUN(conv(n, n->cat[l].cv(), WF(n, dec_a(n, l)), n->dh[l].v(), none, B, H, W, 2 * c, c, n->relu, s,
+                        xrl::kConvUpcat, n->uc[l].cv()));
+        } else {
+            XL_RUN(xrl::upsample2(n->uc[l].cv(), n->cat[l].v(c), c, B, H, W, s));
+            XL_RUN(conv(n, n->cat[l].cv(), WF(n, dec_a(n, l)), n->dh[l].v(), none, B, H, W, 2 * c, c, n->relu, s));
+        }
         XL_RUN(conv(n, n->dh[l].cv(), WF(n, dec_b(n, l)), n->dd[l].v(), none, B, H, W, c, c, n->relu, s));
     }
-    XL_RUN(xrl::conv_out(n->dd[0].cv(), WF(n, out_layer(n)), n->ch[0], n->y, (int)(B * npix), s));
+    if (fuse)
+        XL_RUN(xrl::conv_out(n->dd[0].cv(), WF(n, out_layer(n)), n->ch[0], z, (int)(B * npix), s, n->scale, n->gain,
+                             npix));
+    else
+        XL_RUN(xrl::conv_out(n->dd[0].cv(), WF(n, out_layer(n)), n->ch[0], n->y, (int)(B * npix), s));
+    if (z && !fuse) XL_RUN(xrl::unscale(n->y, n->scale, B, npix, n->gain, z, s));
     return hipSuccess;
 }
 
@@ -553,6 +574,13 @@ xrt_status xrt_unet_set_relu(xrt_unet* net, int32_t on)
     return XRT_OK;
 }
 
+xrt_status xrt_unet_set_fusion(xrt_unet* net, int32_t on)
+{
+    if (!net_ok(net) || (on != 0 && on != 1)) return XRT_EINVAL;
+    net->fuse = on != 0;
+    return XRT_OK;
+}
+
 xrt_status xrt_unet_get_gain(const xrt_unet* net, float* gain)
 {
     if (!net_ok(net) || !gain) return XRT_EINVAL;
@@ -573,8 +601,7 @@ xrt_status xrt_unet_apply(xrt_unet* net, const float* r, float* z, int32_t batch
 {
     if (!net_ok(net) || !r || !z || batch < 1 || batch > net->maxB) return XRT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    XL_CHECK(forward(net, r, nullptr, batch, s), "unet forward");
-    XL_CHECK(xrl::unscale(net->y, net->scale, batch, (int64_t)net->H * net->W, net->gain, z, s), "unscale");
+    XL_CHECK(forward(net, r, nullptr, batch, s, z), "unet forward");
     return XRT_OK;
 }
 

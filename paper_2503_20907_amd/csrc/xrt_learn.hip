@@ -45,7 +45,37 @@ constexpr int kXW = kTW + 2;    // staged input pixels per row (1-pixel halo)
 // row so that 8 consecutive rows read at the same q hit 8 distinct bank groups.
 __device__ __forceinline__ int swz(int row, int q) { return row * 32 + 8 * (q ^ ((row >> 1) & 3)); }
 
-template <int COT, bool F32OUT>
+// 8 input channels from ch of the convolution's input at (b, gh, gw), read as
+// ConvArgs::in_mode says
+template <int MODE>
+__device__ __forceinline__ u32x4 conv_in8(const ConvArgs& a, int b, int gh, int gw, int ch)
+{
+    if constexpr (MODE == kConvPool) {
+        const int H2 = 2 * a.H, W2 = 2 * a.W;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const size_t pf = (size_t)(b * H2 + 2 * gh + (t >> 1)) * W2 + 2 * gw + (t & 1);
+            const u32x4 v = ld16(a.x.p + pf * a.x.pitch + ch);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[2 * k] += lo_bf(v[k]);
+                s[2 * k + 1] += hi_bf(v[k]);
+            }
+        }
+        return u32x4{pack2(0.25f * s[0], 0.25f * s[1]), pack2(0.25f * s[2], 0.25f * s[3]),
+                     pack2(0.25f * s[4], 0.25f * s[5]), pack2(0.25f * s[6], 0.25f * s[7])};
+    } else if constexpr (MODE == kConvUpcat) {
+        const int half = a.cin / 2;
+        if (ch >= half) {
+            const size_t pc = (size_t)(b * (a.H / 2) + gh / 2) * (a.W / 2) + gw / 2;
+            return ld16(a.x2.p + pc * a.x2.pitch + ch - half);
+        }
+    }
+    return ld16(a.x.p + ((size_t)(b * a.H + gh) * a.W + gw) * a.x.pitch + ch);
+}
+
+template <int COT, bool F32OUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint16_t xs[(kTR + 2) * kXW * 32];
@@ -71,8 +101,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a)
             const int r = pix / kXW, c = pix - r * kXW;
             const int gh = h0 + r - 1, gw = w0 + c - 1;
             u32x4 val = {0u, 0u, 0u, 0u};
-            if (gh >= 0 && gh < a.H && gw >= 0 && gw < a.W)
-                val = ld16(a.x.p + ((size_t)(b * a.H + gh) * a.W + gw) * a.x.pitch + ci0 + 8 * q);
+            if (gh >= 0 && gh < a.H && gw >= 0 && gw < a.W) val = conv_in8<MODE>(a, b, gh, gw, ci0 + 8 * q);
             st16(xs + swz(pix, q), val);
         }
         for (int v = tid; v < 9 * COT * 4; v += 256) {
@@ -364,7 +393,8 @@ __global__ __launch_bounds__(256) void k_conv_in_wgrad(const float* x, const flo
     }
 }
 
-__global__ void k_conv_out(CView d, const uint16_t* w, int c, float* y, int64_t npix)
+__global__ void k_conv_out(CView d, const uint16_t* w, int c, float* y, int64_t npix, const float* scale, float gain,
+                           int64_t img_npix)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
@@ -378,7 +408,7 @@ __global__ void k_conv_out(CView d, const uint16_t* w, int c, float* y, int64_t 
             acc = fmaf(hi_bf(v[k]), hi_bf(ww[k]), acc);
         }
     }
-    y[p] = acc;
+    y[p] = scale ? acc * (gain / scale[p / img_npix]) : acc;
 }
 
 __global__ void k_conv_out_bwd(CView d, const uint16_t* w, const float* gy, int c, View gd, int64_t npix, int mask)
@@ -892,12 +922,22 @@ hipError_t conv3x3(const ConvArgs& a0, bool f32_out, float* ws, int64_t ws_float
     a.ksplit = k;
     a.kpart = k > 1 ? ws : nullptr;
     const dim3 grid(ntiles, a.B, (a.cout / (wide ? 64 : 32)) * k);
-    if (wide) {
-        if (f32_out) hipLaunchKernelGGL((k_conv3x3<64, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_conv3x3<64, false>), grid, dim3(256), 0, s, a);
+    if (a.in_mode == kConvPool) {
+        if (f32_out) return hipErrorInvalidValue;
+        if (wide) hipLaunchKernelGGL((k_conv3x3<64, false, kConvPool>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<32, false, kConvPool>), grid, dim3(256), 0, s, a);
+    } else if (a.in_mode == kConvUpcat) {
+        if (f32_out || (a.cin / 2) % 32 || !a.x2.p) return hipErrorInvalidValue;
+        if (wide) hipLaunchKernelGGL((k_conv3x3<64, false, kConvUpcat>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<32, false, kConvUpcat>), grid, dim3(256), 0, s, a);
+    } else if (a.in_mode != kConvPlain) {
+        return hipErrorInvalidValue;
+    } else if (wide) {
+        if (f32_out) hipLaunchKernelGGL((k_conv3x3<64, true, kConvPlain>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<64, false, kConvPlain>), grid, dim3(256), 0, s, a);
     } else {
-        if (f32_out) hipLaunchKernelGGL((k_conv3x3<32, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_conv3x3<32, false>), grid, dim3(256), 0, s, a);
+        if (f32_out) hipLaunchKernelGGL((k_conv3x3<32, true, kConvPlain>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_conv3x3<32, false, kConvPlain>), grid, dim3(256), 0, s, a);
     }
     if (k > 1) {
         const int64_t n = (int64_t)a.B * a.H * a.W * (a.cout / 4);
@@ -955,9 +995,12 @@ hipError_t conv_in_wgrad(const float* x, const float* scale, CView g, int c, int
     return hipGetLastError();
 }
 
-hipError_t conv_out(CView d, const uint16_t* w, int c, float* y, int npix, hipStream_t s)
+hipError_t conv_out(CView d, const uint16_t* w, int c, float* y, int npix, hipStream_t s, const float* scale,
+                    float gain, int64_t img_npix)
 {
-    hipLaunchKernelGGL(k_conv_out, dim3(nblk(npix)), dim3(256), 0, s, d, w, c, y, (int64_t)npix);
+    if (scale && img_npix < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_conv_out, dim3(nblk(npix)), dim3(256), 0, s, d, w, c, y, (int64_t)npix, scale, gain,
+                       img_npix);
     return hipGetLastError();
 }
 

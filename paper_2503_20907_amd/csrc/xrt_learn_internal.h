@@ -26,19 +26,31 @@ struct CView {
 //   y[b,h,w,o] = act( sum_{tap,i} x[b, h+ky-1, w+kx-1, i] * w[tap][o][i] ),
 // tap = 3 ky + kx.  act: optional ReLU, then optional mask (y = 0 where the
 // mask tensor is <= 0; the mask has the output's shape and its own pitch).
+// The input x is read in one of three ways (in_mode), so that a pooling or an
+// upsampling feeding the convolution need not be written out first:
+//   kConvPlain  x[b, h, w, i] at the output's size;
+//   kConvPool   the 2x2 average of x at twice the output's size, rounded to
+//               bf16 exactly as avgpool2 writes it;
+//   kConvUpcat  channels i < cin/2 from x at the output's size, channels
+//               i >= cin/2 from x2 at half the size (nearest neighbour),
+//               i.e. the concatenation [x, upsample2(x2)] that upsample2
+//               builds.
+enum { kConvPlain = 0, kConvPool = 1, kConvUpcat = 2 };
 struct ConvArgs {
     CView x;
-    const uint16_t* w;   // [9][cout][cin]
-    void* y;             // bf16 view or float [pixels][ypitch]
-    int ypitch;
-    CView mask;          // p == nullptr: none
-    int B, H, W, cin, cout;
-    int relu;
+    const uint16_t* w = nullptr;   // [9][cout][cin]
+    void* y = nullptr;             // bf16 view or float [pixels][ypitch]
+    int ypitch = 0;
+    CView mask{nullptr, 0};        // p == nullptr: none
+    int B = 0, H = 0, W = 0, cin = 0, cout = 0;
+    int relu = 0;
+    int in_mode = kConvPlain;
+    CView x2{nullptr, 0};          // kConvUpcat: the half-size input
     // split of the input-channel reduction over workgroups (set by conv3x3):
     // ksplit > 1 writes fp32 partial sums kpart[k][pixel][cout], then a
     // reduction applies the activation and mask
-    int ksplit;
-    float* kpart;
+    int ksplit = 1;
+    float* kpart = nullptr;
 };
 
 // Weight gradient of the convolution above: per region of pixels, partial
@@ -65,7 +77,10 @@ hipError_t conv_in(const float* x, const float* scale, const uint16_t* w /*[9][c
 hipError_t conv_in_wgrad(const float* x, const float* scale, CView g, int c, int B, int H, int W,
                          float* part, int* n_regions, hipStream_t s);
 // 1x1 output layer c -> 1 (fp32 out), its input gradient (masked by d > 0 if mask) and weight gradient
-hipError_t conv_out(CView d, const uint16_t* w, int c, float* y, int npix, hipStream_t s);
+// y[p] = sum_i d[p, i] w[i]; with scale != nullptr the output is unscaled on the
+// way out, y[p] = sum * (gain / scale[p / img_npix]), as unscale does.
+hipError_t conv_out(CView d, const uint16_t* w, int c, float* y, int npix, hipStream_t s,
+                    const float* scale = nullptr, float gain = 1.f, int64_t img_npix = 1);
 hipError_t conv_out_bwd(CView d, const uint16_t* w, const float* gy, int c, View gd, int npix, bool mask,
                         hipStream_t s);
 hipError_t conv_out_wgrad(CView d, const float* gy, int c, int npix, float* part, int* n_regions,

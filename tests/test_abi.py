@@ -129,6 +129,7 @@ def test_learn_entry_points_reject_bad_arguments():
     assert lib.xrt_unet_apply(None, 1, 1, 1, None) == L.XRT_EINVAL
     assert lib.xrt_unet_set_gain(None, ctypes.c_float(1.0)) == L.XRT_EINVAL
     assert lib.xrt_unet_set_relu(None, 1) == L.XRT_EINVAL
+    assert lib.xrt_unet_set_fusion(None, 1) == L.XRT_EINVAL
     n = ctypes.c_int64()
     assert lib.xrt_unet_num_params(None, ctypes.byref(n)) == L.XRT_EINVAL
     assert lib.xrt_reg_apply(None, 8, 8, ctypes.c_float(1.0), 1, None) == L.XRT_EINVAL

@@ -141,6 +141,29 @@ def test_unet_zero_residual_maps_to_zero(dev, learn):
     net.close()
 
 
+@pytest.mark.parametrize("levels,H,Wd,B,relu,cap", [(3, 16, 24, 2, True, 0), (4, 64, 96, 3, False, 0),
+                                                      (6, 512, 512, 1, False, 32)])
+def test_fused_apply_is_bitwise_the_unfused_one(dev, learn, levels, H, Wd, B, relu, cap):
+    """xrt_unet_apply with the pooling, upsampling/concatenation and output
+    unscaling read inside the convolutions gives the same bits as with them in
+    kernels of their own (the last case is the reconstruction workload's
+    network: 6 levels of 32 channels at 512^2, whose small levels take the
+    split-K convolutions)."""
+    from paper_2503_20907_amd import _lib
+    print(f"fused apply levels={levels} {H}x{Wd} B={B} relu={relu}", flush=True)
+    net = learn.UNet(H, Wd, levels=levels, base=32, max_batch=B, seed=7, relu=relu, max_channels=cap)
+    r = W.training_fields(B, H, Wd, seed=31).to(dev)
+    z_fused = net.apply(r).clone()
+    _lib.check(_lib.xrt_unet_set_fusion(net.handle, 0), "xrt_unet_set_fusion")
+    z_plain = net.apply(r).clone()
+    _lib.check(_lib.xrt_unet_set_fusion(net.handle, 1), "xrt_unet_set_fusion")
+    z_again = net.apply(r)
+    assert torch.isfinite(z_fused).all() and float(z_fused.abs().max()) > 0
+    assert torch.equal(z_fused, z_plain) and torch.equal(z_fused, z_again)
+    assert _lib.xrt_unet_set_fusion(net.handle, 2) == _lib.XRT_EINVAL
+    net.close()
+
+
 def test_unet_train_step_is_an_adam_sign_step(dev, learn):
     # first Adam step from zero state moves every parameter by lr * g/(|g|+eps),
     # i.e. by -lr sign(g) where |g| >> eps; the sign is checked against the
