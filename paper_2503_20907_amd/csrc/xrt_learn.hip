@@ -338,29 +338,33 @@ __global__ __launch_bounds__(256) void k_conv_in(const float* x, const float* sc
     __shared__ float wl[9 * 256];
     for (int i = threadIdx.x; i < 9 * c; i += 256) wl[i] = bf2f(w[i]);
     __syncthreads();
+    // grid: x over (pixel in the row, 8-channel group), y over image rows
+    // (b H + h), so that no thread divides a 64-bit index
     const int ng = c / 8;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)B * H * W * ng) return;
-    const int g = (int)(idx % ng);
-    const int64_t pix = idx / ng;
-    const int px = (int)(pix % W), h = (int)((pix / W) % H), b = (int)(pix / ((int64_t)W * H));
-    const float s = scale[b];
-    float xin[9];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= W * ng) return;
+    const int g = t % ng, px = t / ng;
+    for (int row = blockIdx.y; row < B * H; row += gridDim.y) {
+        const int h = row % H, b = row / H;
+        const int64_t pix = (int64_t)row * W + px;
+        const float s = scale[b];
+        float xin[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int hh = h + t / 3 - 1, ww = px + t % 3 - 1;
-        xin[t] = (hh >= 0 && hh < H && ww >= 0 && ww < W) ? x[((int64_t)b * H + hh) * W + ww] * s : 0.f;
+        for (int k = 0; k < 9; ++k) {
+            const int hh = h + k / 3 - 1, ww = px + k % 3 - 1;
+            xin[k] = (hh >= 0 && hh < H && ww >= 0 && ww < W) ? x[((int64_t)b * H + hh) * W + ww] * s : 0.f;
+        }
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc = fmaf(xin[k], wl[k * c + 8 * g + j], acc);
+            v[j] = relu ? fmaxf(acc, 0.f) : acc;
+        }
+        st16(y.p + pix * y.pitch + 8 * g,
+             u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])});
     }
-    float v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        float acc = 0.f;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc = fmaf(xin[t], wl[t * c + 8 * g + j], acc);
-        v[j] = relu ? fmaxf(acc, 0.f) : acc;
-    }
-    st16(y.p + pix * y.pitch + 8 * g,
-         u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])});
 }
 
 // part[block][9][c]; thread: channel tid % c, pixel slot tid / c
@@ -372,15 +376,31 @@ __global__ __launch_bounds__(256) void k_conv_in_wgrad(const float* x, const flo
     const int64_t npix = (int64_t)B * H * W;
     const int64_t p0 = (int64_t)blockIdx.x * per_block, p1 = min(npix, p0 + per_block);
     float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // the pixel's coordinates, divided out once and then advanced by nslot
+    int px = 0, h = 0, b = 0;
+    if (p0 + slot < p1) {
+        const int64_t q = p0 + slot;
+        px = (int)(q % W);
+        h = (int)((q / W) % H);
+        b = (int)(q / ((int64_t)W * H));
+    }
     for (int64_t p = p0 + slot; p < p1; p += nslot) {
+        const int cx = px, ch = h, cb = b;
+        px += nslot;
+        while (px >= W) {
+            px -= W;
+            if (++h == H) {
+                h = 0;
+                ++b;
+            }
+        }
         const float gv = bf2f(g.p[p * g.pitch + co]);
         if (gv == 0.f) continue;
-        const int px = (int)(p % W), h = (int)((p / W) % H), b = (int)(p / ((int64_t)W * H));
-        const float gs = gv * scale[b];
+        const float gs = gv * scale[cb];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int hh = h + t / 3 - 1, ww = px + t % 3 - 1;
-            if (hh >= 0 && hh < H && ww >= 0 && ww < W) acc[t] = fmaf(gs, x[((int64_t)b * H + hh) * W + ww], acc[t]);
+            const int hh = ch + t / 3 - 1, ww = cx + t % 3 - 1;
+            if (hh >= 0 && hh < H && ww >= 0 && ww < W) acc[t] = fmaf(gs, x[((int64_t)cb * H + hh) * W + ww], acc[t]);
         }
     }
 #pragma unroll
@@ -535,13 +555,36 @@ __global__ void k_upsample2_T(CView gf, View y, int c, int B, int H, int W)
 }
 
 // ------------------------------------------------------------ reductions etc.
-__global__ void k_reduce_parts(const float* part, int nreg, int64_t n, float* out)
+// out[e] = sum over regions r of part[r][e], in a fixed order: a workgroup
+// takes 32 consecutive e; its 8 thread groups each sum a contiguous eighth of
+// the regions (four interleaved running sums, combined pairwise), and the
+// eight group sums are added in group order.  The result does not depend on
+// the schedule.
+constexpr int kRedE = 32, kRedG = 8;
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* part, int nreg, int64_t n, float* out)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    float s = 0.f;
-    for (int r = 0; r < nreg; ++r) s += part[(int64_t)r * n + e];
-    out[e] = s;
+    __shared__ float sh[kRedG][kRedE];
+    const int j = threadIdx.x % kRedE, grp = threadIdx.x / kRedE;
+    const int64_t e = (int64_t)blockIdx.x * kRedE + j;
+    const int r0 = (int)((int64_t)grp * nreg / kRedG), r1 = (int)((int64_t)(grp + 1) * nreg / kRedG);
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    if (e < n) {
+        int r = r0;
+        for (; r + 4 <= r1; r += 4) {
+            a0 += part[(int64_t)r * n + e];
+            a1 += part[(int64_t)(r + 1) * n + e];
+            a2 += part[(int64_t)(r + 2) * n + e];
+            a3 += part[(int64_t)(r + 3) * n + e];
+        }
+        for (; r < r1; ++r) a0 += part[(int64_t)r * n + e];
+    }
+    sh[grp][j] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (grp == 0 && e < n) {
+        float s = sh[0][j];
+        for (int k = 1; k < kRedG; ++k) s += sh[k][j];
+        out[e] = s;
+    }
 }
 
 __device__ double block_sum(double v, double* sh)
@@ -975,9 +1018,11 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, int* n_regions, hipStream_t s)
 hipError_t conv_in(const float* x, const float* scale, const uint16_t* w, View y, int c, int B, int H, int W,
                    bool relu, hipStream_t s)
 {
-    if (c % 8 || c > 256) return hipErrorInvalidValue;
-    const int64_t n = (int64_t)B * H * W * (c / 8);
-    hipLaunchKernelGGL(k_conv_in, dim3(nblk(n)), dim3(256), 0, s, x, scale, w, y, c, B, H, W, relu ? 1 : 0);
+    if (c % 8 || c > 256 || (int64_t)B * H > INT32_MAX || (int64_t)W * (c / 8) > INT32_MAX)
+        return hipErrorInvalidValue;
+    const unsigned rows = (unsigned)((int64_t)B * H < 65535 ? (int64_t)B * H : 65535);
+    hipLaunchKernelGGL(k_conv_in, dim3(nblk((int64_t)W * (c / 8)), rows), dim3(256), 0, s, x, scale, w, y, c, B, H, W,
+                       relu ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1052,7 +1097,7 @@ hipError_t upsample2_T(CView g, View y, int c, int B, int H, int W, hipStream_t 
 
 hipError_t reduce_parts(const float* part, int nreg, int64_t n, float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(n)), dim3(256), 0, s, part, nreg, n, out);
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + kRedE - 1) / kRedE)), dim3(256), 0, s, part, nreg, n, out);
     return hipGetLastError();
 }
 

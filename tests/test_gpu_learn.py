@@ -389,14 +389,17 @@ def test_linear_preconditioner_beats_cg_on_the_reconstruction_workload(dev, lear
 
 # --------------------------------------------- what the trained network gains
 def test_trained_preconditioner_gain(dev, learn):
-    """Train the preconditioner on a 128^2 cubic problem with operator-made
-    pairs, then compare flexible CG with the network against plain CG on the
-    problem's own right-hand side (noisy parallel-beam data).  The network's
-    steps reduce the residual faster than CG's first steps: training is
-    deterministic for its seed and leaves 0.545 of CG's residual after two
-    steps; the bound 0.6 leaves room for changes in the operator's FP32
-    rounding, which training follows.  Both runs reach 1e-3, checked with the
-    FP64 oracle's operator."""
+    """Train the preconditioner the solver uses (linear U-Net, energy-norm
+    loss; 5 levels of 32 channels, 3000 Adam steps) on a 128^2 cubic problem
+    with operator-made pairs, then compare flexible CG with the network
+    against plain CG on the problem's own right-hand side (noisy parallel-beam
+    data).  Over training seeds 1-7 the network's two steps leave 0.21-0.45
+    of CG's two-step residual and reach 1e-3 in 4-9 steps against CG's 13;
+    training is deterministic for its seed (seed 1: 0.38, 4 steps), and the
+    bounds (0.6; fewer steps than CG) hold for every seed measured, so they
+    do not hang on one training trajectory, which follows the FP32 rounding
+    of the operator and of the gradient sums.  Both runs reach 1e-3, checked
+    with the FP64 oracle's operator."""
     from paper_2503_20907_amd import ops
     print("trained preconditioner 128^2 cubic", flush=True)
     N, n, lam = 128, 3, 1e-2
@@ -408,8 +411,10 @@ def test_trained_preconditioner_gain(dev, learn):
     b = torch.as_tensor(b64.astype(np.float32), device=dev)
     plan = ops.Plan(N, N, n, ops.Lines.from_spec(spec))
     fields = W.training_fields(256, N, N, seed=63, device=dev)
-    net, stats = learn.train_preconditioner(plan, lam, fields, levels=5, base=32, max_channels=128, steps=1500,
-                                            rounds=3, refresh=128, seed=1)
+    val = W.training_fields(4, N, N, seed=64, device=dev)
+    net, stats = learn.train_preconditioner(plan, lam, fields, levels=5, base=32, max_channels=32, steps=3000,
+                                            rounds=3, refresh=128, seed=1, relu=False, loss="energy", lr=2e-4,
+                                            warmup=100, val_fields=val)
     _, cg2 = learn.solve(plan, b, lam, tol=1e-30, maxit=2, history=2)
     _, fl2 = learn.solve(plan, b, lam, tol=1e-30, maxit=2, net=net, history=2)
     print(f"after 2 steps: CG {cg2['history'][-1]:.4f}, learned {fl2['history'][-1]:.4f}; "
@@ -426,6 +431,7 @@ def test_trained_preconditioner_gain(dev, learn):
         res[name] = info
         print(f"{name}: {info['iterations']} steps, {info['operator_applies']} operator applications, "
               f"residual {true_res:.2e}", flush=True)
+    assert res["learned"]["iterations"] < res["cg"]["iterations"]
     net.close()
     plan.close()
 
