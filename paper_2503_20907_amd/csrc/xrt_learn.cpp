@@ -425,7 +425,7 @@ xrt_status xrt_unet_create(int32_t levels, int32_t base, int32_t max_channels, i
             need = xrl::wgrad_regions(B, H, W, rows) * Ly.size();
         } else {
             const int64_t np = (int64_t)B * H * W;
-            const int64_t per = (np + 511) / 512 < 256 ? 256 : (np + 511) / 512;
+            const int64_t per = xrl::per_block_pixels(np);
             need = (np + per - 1) / per * 9 * n->ch[0];
         }
         if (need > part_n) part_n = need;

@@ -394,9 +394,8 @@ __global__ __launch_bounds__(256) void k_conv_in_wgrad(const float* x, const flo
                 ++b;
             }
         }
-        const float gv = bf2f(g.p[p * g.pitch + co]);
-        if (gv == 0.f) continue;
-        const float gs = gv * scale[cb];
+        // no branch on gv == 0: the x loads then need not wait for g's
+        const float gs = bf2f(g.p[p * g.pitch + co]) * scale[cb];
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int hh = ch + t / 3 - 1, ww = cx + t % 3 - 1;
@@ -1026,7 +1025,10 @@ hipError_t conv_in(const float* x, const float* scale, const uint16_t* w, View y
     return hipGetLastError();
 }
 
-static int per_block_pixels(int64_t npix) { return (int)((npix + 511) / 512 < 256 ? 256 : (npix + 511) / 512); }
+// pixels per workgroup of the 1-channel and 1x1 layers' weight gradients:
+// about 4096 workgroups (at least 64 pixels each), so that the loads of many
+// pixels are in flight
+int per_block_pixels(int64_t npix) { return (int)((npix + 4095) / 4096 < 64 ? 64 : (npix + 4095) / 4096); }
 
 hipError_t conv_in_wgrad(const float* x, const float* scale, CView g, int c, int B, int H, int W, float* part,
                          int* n_regions, hipStream_t s)

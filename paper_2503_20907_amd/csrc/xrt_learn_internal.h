@@ -70,6 +70,8 @@ int64_t conv3x3_ws_floats(int B, int H, int W, int cin, int cout);
 hipError_t conv3x3_wgrad(const WgradArgs& a, int* n_regions, hipStream_t s);
 int wgrad_rows(int B, int H, int W, int cin, int cout);
 int64_t wgrad_regions(int B, int H, int W, int rows);
+// pixels per region of the first and last layers' weight gradients
+int per_block_pixels(int64_t npix);
 
 // first layer (one input channel, fp32, scaled per image) and its weight gradient
 hipError_t conv_in(const float* x, const float* scale, const uint16_t* w /*[9][c]*/, View y, int c,
