@@ -170,3 +170,41 @@ def test_paper_piecewise_expansion_with_corrected_bounds():
         for y in np.linspace(-0.1, a[5] + 0.1, 41):
             ours = oracle.footprint(BOX, theta + math.pi / 2, [y - a[5] / 2])[0]
             assert abs(piecewise(y) - ours) < 1e-12, (theta, y)
+
+
+def hat(u, w):
+    """convolution of two centred unit-mass boxes of width w: (1/w)(1 - |u|/w)_+"""
+    u = np.abs(np.asarray(u, np.float64))
+    return np.maximum(1.0 - u / w, 0.0) / w
+
+
+def test_fig2_family_of_projected_box_splines():
+    """The curves of Fig. 2, theta in [-pi/4, pi/4).  Where a direction of the
+    box spline is parallel to the lines, its box projects to width 0 and the
+    footprint is the convolution of the other two boxes, the linear B-spline
+    (hat): theta = 0 leaves widths (1, 1), so (1 - |u|)_+; theta = pi/4 leaves
+    (1/sqrt 2, 1/sqrt 2).  Between them the support half-width
+    (|sin| + |cos| + |sin - cos|)/2 shrinks from sqrt 2 while the peak rises
+    from 1/sqrt 2, every curve has unit mass, and where all three widths are
+    nonzero the curve is C^1: its second differences over h^2 stay bounded as
+    h shrinks, where at the hats' kinks they grow like 1/h."""
+    u = np.linspace(-1.6, 1.6, 3201)
+    assert np.max(np.abs(oracle.footprint(BOX, 0.0, u) - hat(u, 1.0))) < 1e-13
+    assert np.max(np.abs(oracle.footprint(BOX, math.pi / 4, u) - hat(u, 1 / math.sqrt(2)))) < 1e-12
+    ths = np.linspace(-math.pi / 4, math.pi / 4, 33)[:-1]
+    W = np.array([0.5 * (abs(math.sin(t)) + abs(math.cos(t)) + abs(math.sin(t) - math.cos(t))) for t in ths])
+    peak = np.array([oracle.footprint(BOX, t, [0.0])[0] for t in ths])
+    assert abs(W[0] - math.sqrt(2)) < 1e-12 and np.all(np.diff(W) < 0)
+    assert abs(peak[0] - 1 / math.sqrt(2)) < 1e-12 and np.all(np.diff(peak) > 0)
+    for t, w in zip(ths[::4], W[::4]):
+        v = np.linspace(-w, w, 8001)
+        assert abs(np.trapezoid(oracle.footprint(BOX, t, v), v) - 1.0) < 1e-6
+
+    def curvature(t, h):
+        f = oracle.footprint(BOX, t, np.arange(-2.0, 2.0, h))
+        return np.max(np.abs(np.diff(f, 2))) / h ** 2
+
+    for t in (-0.5, -0.2, 0.3, 0.6):
+        assert curvature(t, 1e-4) < 1.01 * curvature(t, 1e-3) + 1e-6
+    for t in (0.0, math.pi / 4):
+        assert curvature(t, 1e-4) > 5 * curvature(t, 1e-3)

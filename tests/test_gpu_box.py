@@ -79,3 +79,32 @@ def test_box_planless_entry_points():
     b = ops.adjoint(s, lines, BOX, 40, 33)
     assert torch.equal(b, plan.adjoint(s))
     plan.close()
+
+
+def test_box_fig2_family_on_gpu():
+    """The GPU forward of one centred coefficient is the footprint itself:
+    over the Fig. 2 family (32 angles in [-pi/4, pi/4), 97 offsets each) it
+    matches the oracle's, and at theta = 0 and pi/4 the textbook hats
+    (1 - |u|)_+ and sqrt2 (1 - sqrt2 |u|)_+ (the two boxes left when the third
+    direction is parallel to the lines)."""
+    from paper_2503_20907_amd import ops
+    print("box fig2 family 9x9 centre coefficient", flush=True)
+    N = 9
+    c = np.zeros((N, N), np.float32)
+    c[N // 2, N // 2] = 1.0
+    ths = np.linspace(-math.pi / 4, math.pi / 4, 33)[:-1]
+    ys = np.linspace(-1.6, 1.6, 97)
+    th = np.repeat(ths, ys.size).astype(np.float32)
+    y = np.tile(ys, ths.size).astype(np.float32)
+    spec = {"kind": "theta_y", "theta": np.concatenate([th, [0.0] * ys.size, [math.pi / 4] * ys.size]).astype(np.float32),
+            "y": np.concatenate([y, ys, ys]).astype(np.float32)}
+    plan = ops.Plan(N, N, BOX, ops.Lines.from_spec(spec))
+    s = plan.forward(torch.as_tensor(c, device="cuda")).cpu().numpy().astype(np.float64)
+    plan.close()
+    m = th.size
+    ref = np.concatenate([oracle.footprint(BOX, float(t), [float(v)]) for t, v in zip(th, y)])
+    assert np.max(np.abs(s[:m] - ref)) < 1e-6
+    yv = ys.astype(np.float32).astype(np.float64)
+    assert np.max(np.abs(s[m:m + ys.size] - np.maximum(1 - np.abs(yv), 0))) < 1e-6
+    r2 = math.sqrt(2)
+    assert np.max(np.abs(s[m + ys.size:] - r2 * np.maximum(1 - r2 * np.abs(yv), 0))) < 1e-6
