@@ -338,33 +338,29 @@ __global__ __launch_bounds__(256) void k_conv_in(const float* x, const float* sc
     __shared__ float wl[9 * 256];
     for (int i = threadIdx.x; i < 9 * c; i += 256) wl[i] = bf2f(w[i]);
     __syncthreads();
-    // grid: x over (pixel in the row, 8-channel group), y over image rows
-    // (b H + h), so that no thread divides a 64-bit index
     const int ng = c / 8;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= W * ng) return;
-    const int g = t % ng, px = t / ng;
-    for (int row = blockIdx.y; row < B * H; row += gridDim.y) {
-        const int h = row % H, b = row / H;
-        const int64_t pix = (int64_t)row * W + px;
-        const float s = scale[b];
-        float xin[9];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * H * W * ng) return;
+    const int g = (int)(idx % ng);
+    const int64_t pix = idx / ng;
+    const int px = (int)(pix % W), h = (int)((pix / W) % H), b = (int)(pix / ((int64_t)W * H));
+    const float s = scale[b];
+    float xin[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const int hh = h + k / 3 - 1, ww = px + k % 3 - 1;
-            xin[k] = (hh >= 0 && hh < H && ww >= 0 && ww < W) ? x[((int64_t)b * H + hh) * W + ww] * s : 0.f;
-        }
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            float acc = 0.f;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) acc = fmaf(xin[k], wl[k * c + 8 * g + j], acc);
-            v[j] = relu ? fmaxf(acc, 0.f) : acc;
-        }
-        st16(y.p + pix * y.pitch + 8 * g,
-             u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])});
+    for (int t = 0; t < 9; ++t) {
+        const int hh = h + t / 3 - 1, ww = px + t % 3 - 1;
+        xin[t] = (hh >= 0 && hh < H && ww >= 0 && ww < W) ? x[((int64_t)b * H + hh) * W + ww] * s : 0.f;
     }
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc = fmaf(xin[t], wl[t * c + 8 * g + j], acc);
+        v[j] = relu ? fmaxf(acc, 0.f) : acc;
+    }
+    st16(y.p + pix * y.pitch + 8 * g,
+         u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])});
 }
 
 // part[block][9][c]; thread: channel tid % c, pixel slot tid / c
@@ -1017,11 +1013,9 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, int* n_regions, hipStream_t s)
 hipError_t conv_in(const float* x, const float* scale, const uint16_t* w, View y, int c, int B, int H, int W,
                    bool relu, hipStream_t s)
 {
-    if (c % 8 || c > 256 || (int64_t)B * H > INT32_MAX || (int64_t)W * (c / 8) > INT32_MAX)
-        return hipErrorInvalidValue;
-    const unsigned rows = (unsigned)((int64_t)B * H < 65535 ? (int64_t)B * H : 65535);
-    hipLaunchKernelGGL(k_conv_in, dim3(nblk((int64_t)W * (c / 8)), rows), dim3(256), 0, s, x, scale, w, y, c, B, H, W,
-                       relu ? 1 : 0);
+    if (c % 8 || c > 256) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)B * H * W * (c / 8);
+    hipLaunchKernelGGL(k_conv_in, dim3(nblk(n)), dim3(256), 0, s, x, scale, w, y, c, B, H, W, relu ? 1 : 0);
     return hipGetLastError();
 }
 
