@@ -157,6 +157,7 @@ void plan_init(xrt_plan* p, xrt_grid g, int degree, int64_t m, bool split_tiles)
     p->pitch_h = round_up(g.ny + 2 * kPad, 16);
     p->strips_v = (g.ny + kStrip - 1) / kStrip;
     p->strips_h = (g.nx + kStrip - 1) / kStrip;
+    p->fwd_sub = 1;
     // split each adjoint tile's candidate lines over up to 8 workgroups
     // (partial images, summed in a fixed order), aiming at kAdjUnits
     // workgroups per pass: with few units per compute unit the tiles that
@@ -255,9 +256,7 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
         const int ns = std::max(p->strips_v, p->strips_h);
         const size_t sums = (size_t)ns * (size_t)m * sizeof(float);
         p->fwd_persist = own_buffers && !plain && sums <= kMaxStripSums ? 1 : 0;
-        if (p->fwd_persist) {
-            p->spart = al.get<float>((size_t)ns * (size_t)m);
-            p->fctr = al.get<unsigned int>(1);
+        if (own_buffers) {
             int dev = 0, cus = 0;
             if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
@@ -266,6 +265,22 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
             // two lines per thread and item, unless that leaves fewer than
             // four items per workgroup (small problems: one line per thread)
             p->fwd_lpi = (int64_t)ns * (m / (2 * kBlock)) >= 4 * (int64_t)p->fwd_grid ? 2 * kBlock : kBlock;
+            // small problems: items of a half or a quarter strip while there
+            // are fewer than two items per workgroup, so that the last round
+            // of items is short (512^2 cubic, 138,240 lines: 2,160 whole-strip
+            // items for 2,048 workgroups took two full rounds, 0.139 ms per
+            // forward call; half strips 0.125 ms; quarter strips, with each
+            // line's setup repeated per part, 0.139 ms again).  The launches
+            // per strip use the same parts, so both schedules add the same
+            // partial sums in the same order.
+            const int64_t items = (int64_t)ns * ((m + p->fwd_lpi - 1) / p->fwd_lpi);
+            while (p->fwd_sub < 4 && items * p->fwd_sub < 2 * (int64_t)p->fwd_grid &&
+                   sums * (size_t)(2 * p->fwd_sub) <= kMaxStripSums)
+                p->fwd_sub *= 2;
+        }
+        if (p->fwd_persist) {
+            p->spart = al.get<float>((size_t)ns * (size_t)p->fwd_sub * (size_t)m);
+            p->fctr = al.get<unsigned int>(1);
         } else if (own_buffers) {
             p->part = al.get<double>((size_t)m);
         }

@@ -186,6 +186,7 @@ struct xrt_plan {
     int fwd_persist;           // 1: one persistent forward launch (spart); 0: one launch per strip (part)
     int fwd_grid;              // workgroups of the persistent launch
     int fwd_lpi;               // lines per work item of the persistent launch
+    int fwd_sub;               // parts per strip of the persistent launch's items (1, 2, 4)
     double* part;              // [m] running sums over the strips (fwd_persist = 0)
     float* spart;              // [max strips][m] per-strip sums (fwd_persist = 1)
     unsigned int* fctr;        // work counter of the persistent launch

@@ -636,8 +636,10 @@ struct FwdArgs {
     unsigned int* counter;   // work counter of the persistent launch
     int persist;             // 1: persistent launch (spart), 0: one launch per strip (part)
     int lines_per_item;      // persistent launch: lines per work item (a multiple of kBlock)
+    int sub;                 // persistent launch: parts of kStrip / sub rows per strip (1, 2, 4)
     int strips_v, strips_h;
-    int strip;     // strip of this launch (one launch per strip)
+    int strip;     // strip of this launch (one launch per strip part)
+    int q;         // part of the strip (of sub) of this launch
     int nblk, nblk_pad;
 };
 
@@ -735,10 +737,14 @@ __device__ inline float fwd_walk_box(double q, double kap, int ja, int jb, const
 // Sum of line k over the rows of strip `st` that it reaches (times
 // tap_scale<N>); [*ja, *jb] is that row range (empty when *ja > *jb).  The
 // lanes of a wave that call it together share the knot-slot count.
+// Line k's sum over the rows of part q (of nsub) of strip st: rows
+// [st kStrip + q kStrip / nsub, st kStrip + (q + 1) kStrip / nsub).
 template <int N, bool VERT>
-__device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, int* ja_out, int* jb_out)
+__device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, int* ja_out, int* jb_out, int q = 0,
+                                      int nsub = 1)
 {
     const int strip = st;
+    const int rlo = strip * kStrip + q * (kStrip / nsub), rhi = rlo + kStrip / nsub - 1;
     const double xc = A.xc[k], kap = A.kap[k];
     const int nmaj = VERT ? A.ny : A.nx, nmin = VERT ? A.nx : A.ny;
     const int pitch = VERT ? A.pitch_v : A.pitch_h;
@@ -754,8 +760,8 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, int* 
         // the footprint reaches 1 (kappa >= 0) or 1 + |kappa| minor cells
         int jlo, jhi;
         row_range(x0, kap, 1.0 / kap, kap >= 0.0 ? 1.0 : 1.0 - kap, nmaj, nmin, &jlo, &jhi);
-        ja = max(jlo, strip * kStrip);
-        jb = min(jhi, strip * kStrip + kStrip - 1);
+        ja = max(jlo, rlo);
+        jb = min(jhi, rhi);
         const BoxRow bk = box_row(kap);
         const bool neg = __ballot(ja <= jb && bk.neg) != 0ull;
         if (ja <= jb) {
@@ -767,8 +773,8 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, int* 
         const double H = 0.5 * (N + 1);
         int jlo, jhi;
         row_range(x0, kap, 1.0 / kap, H * (1.0 + fabs(kap)), nmaj, nmin, &jlo, &jhi);
-        ja = max(jlo, strip * kStrip);
-        jb = min(jhi, strip * kStrip + kStrip - 1);
+        ja = max(jlo, rlo);
+        jb = min(jhi, rhi);
         const LineConst lc = line_const<N>(kap);
         const int S = wave_slots<N>(ja <= jb ? lc.slots : 1);
         if (ja <= jb) {
@@ -808,8 +814,8 @@ __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
     const int64_t k = first + (int64_t)lb * kBlock + threadIdx.x;
     if (k >= end) return;
     int ja, jb;
-    const float acc = fwd_strip_sum<N, VERT>(A, k, strip, &ja, &jb);
-    if (strip == 0) A.part[k] = (double)acc;
+    const float acc = fwd_strip_sum<N, VERT>(A, k, strip, &ja, &jb, A.q, A.sub);
+    if (strip == 0 && A.q == 0) A.part[k] = (double)acc;
     else if (ja <= jb) A.part[k] += (double)acc;
 }
 
@@ -833,26 +839,28 @@ __global__ void __launch_bounds__(kBlock) k_forward_persist(FwdArgs A)
 {
     __shared__ int s_item;
     const int64_t m_vert = A.hdr->m_vert, m_valid = A.hdr->m_valid;
-    const int lpi = A.lines_per_item;
+    const int lpi = A.lines_per_item, nsub = A.sub;
     const int64_t nbv = (m_vert + lpi - 1) / lpi;
     const int64_t nbh = (m_valid - m_vert + lpi - 1) / lpi;
-    const int64_t items_v = nbv * A.strips_v, items = items_v + nbh * A.strips_h;
+    const int64_t items_v = nbv * A.strips_v * nsub, items = items_v + nbh * A.strips_h * nsub;
     for (;;) {
         const int it = next_item(A.counter, &s_item);
         if (it >= items) break;
         const bool vert = it < items_v;   // uniform over the workgroup
         const int64_t li = vert ? it : it - items_v;
         const int64_t nb = vert ? nbv : nbh;
-        const int st = (int)(li / nb);
-        const int64_t first = (vert ? 0 : m_vert) + (li - st * nb) * lpi;
+        // item li: strip part sq = st nsub + q, then the run of lines; a
+        // strip's parts follow each other, so the items in flight share it
+        const int sq = (int)(li / nb), st = sq / nsub, q = sq - st * nsub;
+        const int64_t first = (vert ? 0 : m_vert) + (li - (int64_t)sq * nb) * lpi;
         const int64_t end = vert ? m_vert : m_valid;
         for (int sub = 0; sub < lpi; sub += kBlock) {
             const int64_t k = first + sub + threadIdx.x;
             if (k < end) {
                 int ja, jb;
-                const float acc = vert ? fwd_strip_sum<N, true>(A, k, st, &ja, &jb)
-                                       : fwd_strip_sum<N, false>(A, k, st, &ja, &jb);
-                A.spart[(int64_t)st * A.m + k] = acc;
+                const float acc = vert ? fwd_strip_sum<N, true>(A, k, st, &ja, &jb, q, nsub)
+                                       : fwd_strip_sum<N, false>(A, k, st, &ja, &jb, q, nsub);
+                A.spart[(int64_t)sq * A.m + k] = acc;
             }
         }
     }
@@ -870,8 +878,8 @@ __global__ void __launch_bounds__(kBlock) k_fwd_reduce(FwdArgs A)
     if (k < m_valid) {
         double acc;
         if (A.persist) {
-            // the strip sums in strip order, as the launches per strip add them
-            const int ns = k < A.hdr->m_vert ? A.strips_v : A.strips_h;
+            // the strip (part) sums in strip order, as the launches per strip add them
+            const int ns = (k < A.hdr->m_vert ? A.strips_v : A.strips_h) * A.sub;
             acc = (double)A.spart[k];
             for (int st = 1; st < ns; ++st) acc += (double)A.spart[(int64_t)st * A.m + k];
         } else {
@@ -1814,9 +1822,11 @@ static FwdArgs make_fwd_args(const xrt_plan* p, float* sino)
     a.counter = p->fctr;
     a.persist = p->fwd_persist;
     a.lines_per_item = p->fwd_lpi;
+    a.sub = p->fwd_sub;
     a.strips_v = p->strips_v;
     a.strips_h = p->strips_h;
     a.strip = 0;
+    a.q = 0;
     a.nblk = (int)((p->m + kBlock - 1) / kBlock);
     a.nblk_pad = (a.nblk + 7) / 8 * 8;
     return a;
@@ -1864,8 +1874,10 @@ static hipError_t forward_n(const xrt_plan* p, float* sino, hipStream_t s)
     // only: the grid of each launch covers all m lines and blocks past the
     // launch's range return at once
     const int ns = p->strips_v > p->strips_h ? p->strips_v : p->strips_h;
-    for (int st = 0; st < ns; ++st) {
+    for (int sq = 0; sq < ns * p->fwd_sub; ++sq) {
+        const int st = sq / p->fwd_sub;
         a.strip = st;
+        a.q = sq - st * p->fwd_sub;
         if (st < p->strips_v) {
             hipLaunchKernelGGL((k_forward<N, true>), dim3((unsigned)a.nblk_pad), dim3(kBlock), 0, s, a);
             hipError_t e = hipGetLastError();
