@@ -23,6 +23,8 @@ constexpr size_t kMaxStripSums = (size_t)4 << 30;
 constexpr int kFwdBlocksPerCU = 8;
 // adjoint workgroups per orientation pass that the tile split aims at
 constexpr int64_t kAdjUnits = 12288;
+// resident adjoint workgroups per CU: the kernels' waves per SIMD (XRT_ADJ_WAVES)
+constexpr int64_t kAdjWavesPerSimd = 5;
 
 thread_local char g_last_error[256] = "";
 
@@ -165,6 +167,13 @@ void plan_init(xrt_plan* p, xrt_grid g, int degree, int64_t m, bool split_tiles)
     // adjoint 27.9 ms unsplit, 25.4 ms split 6 ways)
     const int64_t tiles = (int64_t)((g.nx + kTileI - 1) / kTileI) * ((g.ny + kTileJ - 1) / kTileJ);
     p->adj_split = split_tiles ? (int)std::min<int64_t>(8, (kAdjUnits + tiles - 1) / tiles) : 1;
+    // both passes in one launch when one pass's workgroups would not fill the
+    // GPU's resident slots (kAdjWavesPerSimd workgroups of 4 waves per CU)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    p->adj_merge = p->adj_split > 1 && tiles * p->adj_split < (int64_t)cus * kAdjWavesPerSimd ? 1 : 0;
 }
 
 hipError_t plan_build(const xrt_plan* p, const xrt_lines* lines, const PlanTemps& t, hipStream_t s,
@@ -284,7 +293,9 @@ xrt_status plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* str
         } else if (own_buffers) {
             p->part = al.get<double>((size_t)m);
         }
-        p->adj_part = p->adj_split > 1 ? al.get<float>((size_t)p->adj_split * g.nx * g.ny) : nullptr;
+        p->adj_part = p->adj_split > 1
+                          ? al.get<float>((size_t)(p->adj_merge ? 2 : 1) * p->adj_split * g.nx * g.ny)
+                          : nullptr;
     }
     // temporaries
     PlanTemps t;

@@ -191,5 +191,6 @@ struct xrt_plan {
     float* spart;              // [max strips][m] per-strip sums (fwd_persist = 1)
     unsigned int* fctr;        // work counter of the persistent launch
     int adj_split;             // workgroups sharing one adjoint tile's candidate lines
-    float* adj_part;           // [adj_split][ny][nx] partial images (adj_split > 1)
+    float* adj_part;           // [adj_split][ny][nx] partial images (adj_split > 1), twice that with adj_merge
+    int adj_merge;             // 1: both adjoint passes in one launch (grids too small to fill the GPU per pass)
 };

@@ -1453,6 +1453,24 @@ __global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint(AdjArgs A)
     adj_tile<N, MODE>(A, tile, (int)blockIdx.y, sh);
 }
 
+// Both passes in one launch (small grids, where one pass's workgroups do
+// not fill the GPU): blockIdx.y < split runs the vertical lines' tile parts,
+// the rest the horizontal lines' on the transposed tiles; every part writes
+// its own partial image (V.part, then H.part), which one reduction adds in
+// order.
+template <int N>
+__global__ void __launch_bounds__(kBlock) XRT_ADJ_ATTR k_adjoint_both(AdjArgs V, AdjArgs H)
+{
+    __shared__ AdjShared sh;
+    const bool vert = (int)blockIdx.y < V.split;   // uniform per block
+    const AdjArgs& A = vert ? V : H;
+    if ((int)blockIdx.x >= A.ntiles_pad) return;
+    const int tile = xcd_logical(blockIdx.x, A.ntiles_pad);
+    if (tile >= A.ntiles) return;
+    if (vert) adj_tile<N, kAdjVert>(V, tile, (int)blockIdx.y, sh);
+    else adj_tile<N, kAdjHoriz>(H, tile, (int)blockIdx.y - V.split, sh);
+}
+
 // Lines whose (sorted, scaled) sinogram value is NaN or infinite: the
 // adjoint's fixed-point sums leave them out, and every pixel inside the
 // line's footprint support, |X(j) - i| < W in each row j it reaches, is set
@@ -1957,6 +1975,23 @@ hipError_t launch_adj_nonfinite(const xrt_plan* p, const float* sw, float* out, 
 template <int N>
 static hipError_t adjoint_n(const xrt_plan* p, float* out, hipStream_t s)
 {
+    if (p->adj_merge) {
+        const int64_t npix = (int64_t)p->g.nx * p->g.ny;
+        AdjArgs v = make_adj_args(p, out, kAdjVert), h = make_adj_args(p, out, kAdjHoriz);
+        v.split = h.split = p->adj_split;
+        v.part = p->adj_part;
+        h.part = p->adj_part + (size_t)p->adj_split * (size_t)npix;
+        const int gx = v.ntiles_pad > h.ntiles_pad ? v.ntiles_pad : h.ntiles_pad;
+        hipLaunchKernelGGL(k_adjoint_both<N>, dim3((unsigned)gx, (unsigned)(2 * p->adj_split)), dim3(kBlock), 0, s,
+                           v, h);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_adj_reduce, dim3((unsigned)((npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           p->adj_part, 2 * p->adj_split, npix, 0, out);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_adj_nonfinite(p, p->sw, out, s);
+    }
     hipError_t e = adjoint_pass<N, kAdjVert>(p, out, s);
     if (e != hipSuccess) return e;
     e = adjoint_pass<N, kAdjHoriz>(p, out, s);

@@ -128,7 +128,7 @@ extern "C" xrt_status xrt_adjoint_noalloc(const float* sino, const xrt_lines* li
     const size_t temps_end = c.used;
     c.used = shared_at;
     p.sw = c.take<float>(m);
-    p.adj_part = p.adj_split > 1 ? c.take<float>((size_t)p.adj_split * npix) : nullptr;
+    p.adj_part = p.adj_split > 1 ? c.take<float>((size_t)(p.adj_merge ? 2 : 1) * p.adj_split * npix) : nullptr;
     const size_t need = std::max(temps_end, c.used);
     if (need > kNoAllocBytes) {
         char msg[200];
