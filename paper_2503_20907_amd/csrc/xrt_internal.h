@@ -183,7 +183,7 @@ struct xrt_plan {
     float *cv, *dv, *ch, *dh;  // coefficient / difference layouts
     float* sw;                 // sinogram in sorted order, scaled
     int strips_v, strips_h;    // strips of kStrip rows, per orientation
-    int fwd_persist;           // 1: one persistent forward launch (spart); 0: one launch per strip (part)
+    int fwd_persist;           // 1: one persistent forward launch (spart); 0: one launch per strip part (part)
     int fwd_grid;              // workgroups of the persistent launch
     int fwd_lpi;               // lines per work item of the persistent launch
     int fwd_sub;               // parts per strip of the persistent launch's items (1, 2, 4)

@@ -31,13 +31,15 @@
 // every line adds W_d s to the cells J-d and r^n E(.) s to the knots K of an
 // LDS tile, and the tile's output is A + Delta^T K.  One launch takes the
 // vertical lines and writes the image, a second one the horizontal lines and
-// adds into it.  A tile's candidate lines are shared by up to 8 workgroups
-// (every split-th chunk each), whose partial images k_adj_reduce adds in a
-// fixed order.
+// adds into it (on grids too small to fill the GPU per pass, one launch runs
+// both).  A tile's candidate lines are shared by up to 8 workgroups (every
+// split-th chunk each), whose partial images k_adj_reduce adds in a fixed
+// order.
 //
 // The forward is one persistent launch: workgroups take (orientation, strip,
 // run of lines) items in strip order, and each line's strip sums are added
-// in strip order afterwards (k_fwd_reduce).
+// in strip order afterwards (k_fwd_reduce).  On small problems an item covers
+// a half or a quarter strip, and the parts' sums are added in the same way.
 //
 // The 3-directional box spline (basis code kBox3) uses the same schedules
 // with its own row arithmetic (box_row, box_F): a telescoped row sum over two
@@ -631,10 +633,10 @@ struct FwdArgs {
     int nx, ny;
     double h;
     float* sino;
-    double* part;            // [m] sums over the strips done so far (one launch per strip)
-    float* spart;            // [strips][m] per-strip sums (persistent launch)
+    double* part;            // [m] sums over the strip parts done so far (one launch per part)
+    float* spart;            // [strips * sub][m] per-part sums (persistent launch)
     unsigned int* counter;   // work counter of the persistent launch
-    int persist;             // 1: persistent launch (spart), 0: one launch per strip (part)
+    int persist;             // 1: persistent launch (spart), 0: one launch per strip part (part)
     int lines_per_item;      // persistent launch: lines per work item (a multiple of kBlock)
     int sub;                 // persistent launch: parts of kStrip / sub rows per strip (1, 2, 4)
     int strips_v, strips_h;
@@ -790,12 +792,13 @@ __device__ inline float fwd_strip_sum(const FwdArgs& A, int64_t k, int st, int* 
     return acc;
 }
 
-// Forward, one launch per (orientation, strip of kStrip rows): the blocks in
-// flight at any time read one strip of the layout, which stays in L2.  The
-// launches of one orientation run in strip order and each adds its partial
-// sums into part[k] (the first one writes), so the sum is deterministic;
-// k_fwd_reduce scales and scatters.  Used when the persistent launch's
-// per-strip sums would take too much memory.
+// Forward, one launch per (orientation, strip of kStrip rows, part of it):
+// the blocks in flight at any time read one strip of the layout, which stays
+// in L2.  The launches of one orientation run in strip order and each adds
+// its partial sums into part[k] (the first one writes), so the sum is
+// deterministic and equals the persistent launch's; k_fwd_reduce scales and
+// scatters.  Used when the persistent launch's per-part sums would take too
+// much memory.
 template <int N, bool VERT>
 __global__ void __launch_bounds__(kBlock) k_forward(FwdArgs A)
 {
