@@ -119,8 +119,9 @@ xrt_status xrt_adjoint(const float* sino, const xrt_lines* lines, int degree, xr
  * device allocation or free and no synchronisation.  Its temporary plan
  * lives in one static device array of 64 MiB that each GPU the library runs
  * on holds until the process ends (about 56 B per line, 8 B per
- * (orientation, slope bin, crossing bucket) key and up to 8 partial images:
- * e.g. 700,000 lines on a 512^2 grid); larger problems return XRT_ESIZE.
+ * (orientation, slope bin, crossing bucket) key and up to 16 partial images,
+ * 8 per pass, both passes sharing one launch on small grids: e.g. 700,000
+ * lines on a 512^2 grid); larger problems return XRT_ESIZE.
  * The first call on a device sets the array up (looks up its address,
  * synchronously).  Every call on one GPU
  * shares that array: calls that overlap on one GPU race and must be
@@ -134,9 +135,10 @@ xrt_status xrt_adjoint_noalloc(const float* sino, const xrt_lines* lines, int de
  * the call only.  On error *out is NULL and nothing stays allocated.
  * Device memory held by the plan: about 24 B per line (sorted line records,
  * scaled sinogram), 4 B per line and strip of 128 grid rows (the forward's
- * strip sums; 8 B per line instead when that would pass 4 GiB), four padded
- * copies of the coefficient grid, up to 8 partial images, and 4 B per
- * (orientation, slope bin, crossing bucket) key. */
+ * strip sums; per half or quarter strip on small problems; 8 B per line
+ * instead when that would pass 4 GiB), four padded copies of the
+ * coefficient grid, up to 16 partial images (8 per adjoint pass), and 4 B
+ * per (orientation, slope bin, crossing bucket) key. */
 xrt_status xrt_plan_create(xrt_grid g, int degree, const xrt_lines* lines, void* stream,
                            xrt_plan** out);
 
