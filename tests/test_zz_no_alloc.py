@@ -75,3 +75,20 @@ def test_noalloc_empty_and_too_large(torch):
     st = L.xrt_adjoint_noalloc(s.data_ptr(), lc, 3, L.XrtGrid(64, 64, 1.0, 0.0, 0.0), out.data_ptr(), stream)
     assert st == L.XRT_ESIZE
     assert "maximum" in L.last_error()
+
+
+def test_noalloc_holds_the_documented_example(torch):
+    """The header's example fits the array: 700,000 lines on a 512^2 grid
+    (a small grid, so the two adjoint passes share one launch and 16 partial
+    images), and the result equals xrt_adjoint's bit for bit."""
+    from paper_2503_20907_amd import _lib as L
+    print("case: no-alloc adjoint 512x512, 700000 lines, cubic", flush=True)
+    rng = np.random.default_rng(1301)
+    m, n = 700_000, 512
+    th = rng.uniform(-math.pi, 2 * math.pi, m).astype(np.float32)
+    y = rng.uniform(-0.7 * n, 0.7 * n, m).astype(np.float32)
+    lc, keep = _lines(L, torch, th, y)
+    s = torch.as_tensor(rng.normal(size=m).astype(np.float32), device="cuda")
+    a, b = _both(L, torch, s, lc, 3, L.XrtGrid(n, n, 1.0, 0.0, 0.0), n, n)
+    assert torch.equal(a, b)
+    assert float(b.abs().max()) > 0
